@@ -1,0 +1,157 @@
+"""Python access to the CPU oracle (oracle/oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg.  The library path never imports it.
+
+All array arguments are numpy uint64 arrays; results are new numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build_oracle
+
+_lib = None
+_U64P = ctypes.POINTER(ctypes.c_uint64)
+_U64 = ctypes.c_uint64
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = build_oracle.OUT
+        if not os.path.exists(path):
+            build_oracle.build()
+        L = ctypes.CDLL(path)
+        for name, res, args in [
+            ("or_mulmod", _U64, [_U64, _U64, _U64]),
+            ("or_addmod", _U64, [_U64, _U64, _U64]),
+            ("or_powmod", _U64, [_U64, _U64, _U64]),
+            ("or_invmod", _U64, [_U64, _U64]),
+            ("or_is_prime", ctypes.c_int, [_U64]),
+            ("or_brv", _U64, [_U64, ctypes.c_int]),
+            ("or_min_root", _U64, [_U64, _U64]),
+            ("or_find_primes", _U64, [ctypes.c_int, _U64, _U64, _U64P]),
+            ("or_find_primes_up", _U64, [ctypes.c_int, _U64, _U64, _U64P]),
+            ("or_eltwise_add", None, [_U64P, _U64P, _U64P, _U64, _U64]),
+            ("or_eltwise_mult", None, [_U64P, _U64P, _U64P, _U64, _U64]),
+            ("or_ntt_forward", None, [_U64P, _U64P, _U64, _U64, _U64, ctypes.c_int]),
+            ("or_ntt_inverse", None, [_U64P, _U64P, _U64, _U64, _U64, ctypes.c_int]),
+            ("or_ntt_forward_at", None, [_U64P, _U64P, _U64P, _U64, _U64, _U64, _U64, ctypes.c_int]),
+            ("or_ntt_inverse_at", None, [_U64P, _U64P, _U64P, _U64, _U64, _U64, _U64, ctypes.c_int]),
+            ("or_negacyclic_mul", None, [_U64P, _U64P, _U64P, _U64, _U64, ctypes.c_int]),
+            ("or_negacyclic_mul_at", None, [_U64P, _U64P, _U64P, _U64P, _U64, _U64, _U64, ctypes.c_int]),
+            ("or_harvey_forward", None, [_U64P, _U64, _U64, _U64, ctypes.c_int]),
+            ("or_harvey_inverse", None, [_U64P, _U64, _U64, _U64, ctypes.c_int]),
+        ]:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _threads(n):
+    return int(n) if n else max(1, min(16, os.cpu_count() or 1))
+
+
+def _arr(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint64))
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(_U64P)
+
+
+def mulmod(a, b, q): return int(lib().or_mulmod(a, b, q))
+def addmod(a, b, q): return int(lib().or_addmod(a, b, q))
+def powmod(a, e, q): return int(lib().or_powmod(a, e, q))
+def invmod(a, q): return int(lib().or_invmod(a, q))
+def is_prime(n): return bool(lib().or_is_prime(n))
+def brv(i, logn): return int(lib().or_brv(i, logn))
+def min_root(N, q): return int(lib().or_min_root(N, q))
+
+
+def find_primes(bits: int, m: int, count: int) -> list:
+    """The `count` largest primes below 2^bits that are 1 mod m, descending."""
+    out = np.zeros(count, dtype=np.uint64)
+    k = lib().or_find_primes(bits, m, count, _p(out))
+    return [int(x) for x in out[:k]]
+
+
+def find_primes_up(bits: int, m: int, count: int) -> list:
+    """The `count` smallest primes of exactly `bits` bits that are 1 mod m, ascending."""
+    out = np.zeros(count, dtype=np.uint64)
+    k = lib().or_find_primes_up(bits, m, count, _p(out))
+    return [int(x) for x in out[:k]]
+
+
+def eltwise_add(a, b, q):
+    a, b = _arr(a), _arr(b)
+    c = np.empty_like(a)
+    lib().or_eltwise_add(_p(c), _p(a), _p(b), a.size, q)
+    return c
+
+
+def eltwise_mult(a, b, q):
+    a, b = _arr(a), _arr(b)
+    c = np.empty_like(a)
+    lib().or_eltwise_mult(_p(c), _p(a), _p(b), a.size, q)
+    return c
+
+
+def ntt_forward(a, q, psi, threads=None):
+    a = _arr(a)
+    out = np.empty_like(a)
+    lib().or_ntt_forward(_p(out), _p(a), a.size, q, psi, _threads(threads))
+    return out
+
+
+def ntt_inverse(a, q, psi, threads=None):
+    a = _arr(a)
+    out = np.empty_like(a)
+    lib().or_ntt_inverse(_p(out), _p(a), a.size, q, psi, _threads(threads))
+    return out
+
+
+def ntt_forward_at(a, idx, q, psi, threads=None):
+    a, idx = _arr(a), _arr(idx)
+    out = np.empty(idx.size, dtype=np.uint64)
+    lib().or_ntt_forward_at(_p(out), _p(a), _p(idx), idx.size, a.size, q, psi, _threads(threads))
+    return out
+
+
+def ntt_inverse_at(a, idx, q, psi, threads=None):
+    a, idx = _arr(a), _arr(idx)
+    out = np.empty(idx.size, dtype=np.uint64)
+    lib().or_ntt_inverse_at(_p(out), _p(a), _p(idx), idx.size, a.size, q, psi, _threads(threads))
+    return out
+
+
+def negacyclic_mul(a, b, q, threads=None):
+    a, b = _arr(a), _arr(b)
+    c = np.empty_like(a)
+    lib().or_negacyclic_mul(_p(c), _p(a), _p(b), a.size, q, _threads(threads))
+    return c
+
+
+def negacyclic_mul_at(a, b, idx, q, threads=None):
+    a, b, idx = _arr(a), _arr(b), _arr(idx)
+    c = np.empty(idx.size, dtype=np.uint64)
+    lib().or_negacyclic_mul_at(_p(c), _p(a), _p(b), _p(idx), idx.size, a.size, q, _threads(threads))
+    return c
+
+
+def harvey_forward(a, q, psi, out_f=4):
+    a = _arr(a).copy()
+    lib().or_harvey_forward(_p(a), a.size, q, psi, out_f)
+    return a
+
+
+def harvey_inverse(a, q, psi, out_f=2):
+    a = _arr(a).copy()
+    lib().or_harvey_inverse(_p(a), a.size, q, psi, out_f)
+    return a
