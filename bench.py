@@ -1,0 +1,164 @@
+"""Benchmark of the negacyclic NTT hot path on one MI355X.
+
+One step = one pass of the whole hot path over a batch of RNS polynomials at
+N = 2^14 with 8 limbs of 50-bit primes (q = 1 mod 2N):
+    c   = InvNTT( NTT(a) (.) NTT(b) )         per limb (forward 1->4, forward 1->4
+                                               fused with the modmul, inverse 1->1)
+    acc = acc + c  (mod q)                    element-wise add
+The reported value is forward limb-NTTs per second of whole-step throughput
+(2 forward transforms per limb-product; the inverse, the multiply and the add
+run inside the same timed step).  Inputs are seeded synthetic uniform
+coefficients, resident in device memory before timing starts.
+
+Also reported, on the same JSON line:
+  roofline      the forward transform of one operand batch (the dominant kernel
+                sequence), algorithmic bytes / average duration (HIP events on the
+                launch stream) against 8 TB/s;
+  cpu_baseline  the CPU oracle (O(N^2) direct forward transform) on a bounded
+                sample, timed on this host's cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+
+def load_primes():
+    with open(os.path.join(ROOT, "tests", "golden", "primes.json")) as f:
+        return json.load(f)
+
+
+def gen_operand(tag, N, moduli, B):
+    from synthetic import uniform_mod, unit_seed
+    L = len(moduli)
+    out = np.empty(B * L * N, dtype=np.uint64)
+    for p in range(B):
+        for l, q in enumerate(moduli):
+            out[(p * L + l) * N:(p * L + l + 1) * N] = uniform_mod(unit_seed(tag, p, l, q), N, q)
+    return out
+
+
+def cpu_baseline(N, moduli, psis, budget_s=12.0):
+    """Oracle forward transform (O(N^2) direct sums) over a bounded sample of limbs."""
+    import oracle
+    from synthetic import uniform_mod, unit_seed
+    threads = max(1, min(os.cpu_count() or 1, 16))
+    done, t0 = 0, time.perf_counter()
+    while True:
+        l = done % len(moduli)
+        a = uniform_mod(unit_seed(7, done, moduli[l]), N, moduli[l])
+        oracle.ntt_forward(a, moduli[l], psis[l], threads=threads)
+        done += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": done / el, "unit": "NTT/s", "cores": threads, "kind": "oracle",
+            "sample": "%d limb forward transforms (N=%d, first %d of the 8 primes), O(N^2) direct "
+                      "definition, %d threads, %.1f s" % (done, N, min(done, len(moduli)), threads, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--polys", type=int, default=512, help="RNS polynomials per step")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; the path shards over GPUs by limbs "
+              "with no exchange, but no multi-GPU run is part of it (got --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2103_16400_amd as nt
+
+    primes = load_primes()["rns_16384"]
+    N, moduli, psis = primes["N"], primes["moduli"], primes["psi"]
+    L, B = len(moduli), args.polys
+    dev = torch.device("cuda:0")
+
+    def up(x):
+        return torch.from_numpy(x.view(np.int64)).to(dev)
+
+    a = up(gen_operand(1, N, moduli, B))
+    b = up(gen_operand(2, N, moduli, B))
+    c = torch.empty_like(a)
+    ws = torch.empty_like(a)
+    acc = torch.zeros_like(a)
+    stream = torch.cuda.current_stream()
+    # the forward transform of operand a, timed separately inside each step
+    fa = torch.empty_like(a)
+
+    ev = []
+
+    def step(record):
+        if record:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        nt.ntt_forward_rns(c, a, N, moduli, B, 1, 4, stream=stream)            # NTT(a), lazy [0, 4q)
+        if record:
+            e1.record(stream)
+            ev.append((e0, e1))
+        nt.ntt_forward_rns(fa, b, N, moduli, B, 1, 4, stream=stream)           # NTT(b) ...
+        nt.eltwise_mult_mod_rns(c, c, fa, N, moduli, B, 4, stream=stream)       # ... (.) NTT(a)
+        nt.ntt_inverse_rns(c, c, N, moduli, B, 1, 1, stream=stream)             # InvNTT
+        nt.eltwise_add_mod_rns(acc, acc, c, N, moduli, B, stream=stream)        # acc += a*b
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    fwd_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+
+    limbs = B * L
+    fwd_per_step = 2 * limbs
+    value = fwd_per_step / (wall / args.steps)
+    alg_bytes = 16 * N * limbs + 16 * N * L        # coefficients read+written, one twiddle table per prime
+    achieved = alg_bytes / (fwd_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": "forward NTTs/s at N=2^14 (RNS product pipeline, 8 x 50-bit limbs)",
+        "value": round(value, 1),
+        "unit": "NTT/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "rns_product_n16384_l8", "N": N, "limbs": L, "polys_per_step": B,
+                   "step": "fwd(a) 1->4, fwd(b) 1->4, modmul f=4, inv 1->1, acc add",
+                   "forward_ntts_per_step": fwd_per_step},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "forward NTT of %d limbs (ntt_pass_kernel, all passes)" % limbs,
+                     "avg_ms": round(fwd_ms, 4), "alg_bytes": alg_bytes},
+        "fwd_ntt_rate": round(limbs / (fwd_ms * 1e-3), 1),
+        "products_per_s": round(limbs / (wall / args.steps), 1),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(N, moduli, psis, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * ntt_hip.h -- C ABI of the MI355X (gfx950) negacyclic NTT library.
+ *
+ * The operations are those of "Intel HEXL: Accelerating Homomorphic Encryption
+ * with Intel AVX512-IFMA52" (Boemer, Kim, Seifu, de Souza, Gopal, WAHC 2021):
+ * the forward and inverse negacyclic number-theoretic transform over
+ * Z_q[X]/(X^N + 1) (Section 2.2, Algorithms 2-5, NTT class listing of
+ * Section 4) and the element-wise modular add and multiply on RNS limbs
+ * (Section 2 ring operations, free-function listing of Section 4,
+ * Algorithm 8).  Every call is exact unsigned 64-bit integer arithmetic.
+ *
+ * Conventions shared by every entry point
+ *   - Data pointers are DEVICE pointers owned by the caller, 8-byte aligned
+ *     (256-byte alignment is recommended).  The library never frees them.
+ *   - Calls are asynchronous: work is enqueued on `stream` (NULL = the
+ *     device's default stream) on the device that is current for the calling
+ *     host thread, and the call returns.  The status reports argument errors
+ *     and launch failures only; execution completes at the caller's next
+ *     synchronisation with the stream.
+ *   - result == operand (exactly the same pointer) runs in place, as the
+ *     paper's product listing does.  Any other overlap of an output with an
+ *     input is rejected with NTT_EALIAS.
+ *   - Operand values must lie in [0, input_mod_factor * q).  This is a
+ *     precondition and is not checked on the hot path; values outside the
+ *     range give unspecified (but memory-safe) results.
+ *   - Host-side twiddle tables ("plans") are built once per (device, N, q,
+ *     root) and cached; the first call with a new modulus allocates and
+ *     uploads them.  No call allocates memory once its plans exist.
+ *   - Thread safety: every entry point may be called concurrently from
+ *     several host threads; plans are immutable after creation.
+ *   - Errors never throw across the ABI; they are returned as negative
+ *     ntt_status values.
+ */
+#ifndef NTT_HIP_H
+#define NTT_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int ntt_status;
+
+#define NTT_OK 0
+#define NTT_EINVAL_DEGREE (-1)   /* N not a power of two, or outside [2, 2^17]        */
+#define NTT_EINVAL_MODULUS (-2)  /* q not prime, q != 1 mod 2N, or q outside its range */
+#define NTT_EINVAL_ROOT (-3)     /* root_of_unity is not a primitive 2N-th root mod q  */
+#define NTT_EINVAL_FACTOR (-4)   /* input/output mod factor outside the allowed set    */
+#define NTT_EINVAL_POINTER (-5)  /* a required pointer is NULL                         */
+#define NTT_EALIAS (-6)          /* an output partially overlaps an input              */
+#define NTT_EINVAL_COUNT (-7)    /* a length, limb or polynomial count is invalid      */
+#define NTT_EDEVICE (-8)         /* the HIP runtime reported an error                  */
+#define NTT_ENOMEM (-9)          /* device or host allocation failed                   */
+#define NTT_ENOTFOUND (-10)      /* unknown handle / nothing to report                 */
+#define NTT_EBUSY (-11)          /* admission refused: budget or queue full            */
+
+/* Largest ring degree and limb count the kernels are built for. */
+#define NTT_MAX_LOG_DEGREE 17
+#define NTT_MAX_LIMBS 64
+
+/* Same type as hipStream_t, declared without the HIP headers. */
+typedef struct ihipStream_t* ntt_stream_t;
+
+/* Human-readable text for a status code (static storage, never NULL). */
+const char* ntt_status_string(ntt_status status);
+
+/* Releases every cached plan and library-owned device buffer.  Calls made
+ * afterwards rebuild what they need.  Must not race with other calls. */
+ntt_status ntt_shutdown(void);
+
+/* ---------------------------------------------------------------------------
+ * Plans: the paper's NTT object (Section 4, NTT class listing).  A plan owns
+ * the device-resident tables of one (N, q, psi): psi_rev[k] = psi^brv(k) and
+ * psi^{-1}_rev[k] = psi^{-brv(k)} (Algorithms 2 and 3) with their Shoup
+ * companions W' = floor(W * 2^64 / q) (Algorithms 4 and 5), N^{-1} mod q.
+ *
+ *   N              ring degree, a power of two in [2, 2^17]
+ *   q              prime modulus with q = 1 mod 2N and q < 2^62 (Algorithm 4
+ *                  requires q < beta/4 with beta = 2^64)
+ *   root_of_unity  a primitive 2N-th root psi of unity mod q (psi^N = -1), or
+ *                  0 to use the smallest such root
+ * Errors: NTT_EINVAL_DEGREE, NTT_EINVAL_MODULUS, NTT_EINVAL_ROOT,
+ *         NTT_EINVAL_POINTER, NTT_ENOMEM, NTT_EDEVICE.
+ * The plan belongs to the device current at creation; destroy it with
+ * ntt_plan_destroy once no enqueued work uses it.
+ */
+typedef struct ntt_plan ntt_plan;
+ntt_status ntt_plan_create(ntt_plan** plan, uint64_t N, uint64_t q, uint64_t root_of_unity);
+ntt_status ntt_plan_destroy(ntt_plan* plan);
+/* The root of unity psi a plan uses (0 for a NULL plan). */
+uint64_t ntt_plan_root(const ntt_plan* plan);
+
+/* ---------------------------------------------------------------------------
+ * Forward negacyclic NTT of one limb (Section 2.2; Algorithm 2 with the
+ * Harvey butterfly of Algorithm 4; NTT::ComputeForward of the Section 4
+ * listing).
+ *   result[i] = sum_j operand[j] * psi^((2*brv(i)+1)*j)  (mod q), i < N,
+ * i.e. the output is in bit-reversed order.
+ *   input_mod_factor   1, 2 or 4: operand values lie in [0, f*q)
+ *   output_mod_factor  1 -> result in [0, q);  4 -> result in [0, 4q)
+ *                      (lazy: congruent to the canonical value mod q)
+ * ntt_forward uses the plan of (N, q, smallest psi) from the library cache;
+ * ntt_forward_plan uses an explicit plan.
+ */
+ntt_status ntt_forward(uint64_t* result, const uint64_t* operand, uint64_t N, uint64_t q,
+                       uint64_t input_mod_factor, uint64_t output_mod_factor, ntt_stream_t stream);
+ntt_status ntt_forward_plan(const ntt_plan* plan, uint64_t* result, const uint64_t* operand,
+                            uint64_t input_mod_factor, uint64_t output_mod_factor, ntt_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Inverse negacyclic NTT of one limb (Section 2.2; Algorithm 3 with the
+ * Harvey butterfly of Algorithm 5 and the final multiplication by N^{-1};
+ * NTT::ComputeInverse).  The operand is in bit-reversed order, the result in
+ * natural order:
+ *   result[j] = N^{-1} * sum_i operand[i] * psi^(-(2*brv(i)+1)*j)  (mod q).
+ *   input_mod_factor   1 or 2
+ *   output_mod_factor  1 -> [0, q);  2 -> [0, 2q) (lazy)
+ */
+ntt_status ntt_inverse(uint64_t* result, const uint64_t* operand, uint64_t N, uint64_t q,
+                       uint64_t input_mod_factor, uint64_t output_mod_factor, ntt_stream_t stream);
+ntt_status ntt_inverse_plan(const ntt_plan* plan, uint64_t* result, const uint64_t* operand,
+                            uint64_t input_mod_factor, uint64_t output_mod_factor, ntt_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Element-wise kernels (Section 2; EltwiseMultMod / EltwiseAddMod of the
+ * Section 4 free-function listing).  n is any length >= 1.
+ *
+ * eltwise_mult_mod: result[i] = operand1[i] * operand2[i] mod q, canonical.
+ *   Inputs lie in [0, input_mod_factor * q), input_mod_factor in {1, 2, 4};
+ *   q in [2, 2^62) and input_mod_factor * q < 2^63 (Algorithm 8).  Barrett
+ *   reduction with Q = floor(log2 q) + 1, L = 63 + Q, followed by two
+ *   conditional subtractions (one is not always enough for these Q, L).
+ * eltwise_add_mod: result[i] = (operand1[i] + operand2[i]) mod q, inputs in
+ *   [0, q), q in [2, 2^63 - 1].
+ */
+ntt_status eltwise_mult_mod(uint64_t* result, const uint64_t* operand1, const uint64_t* operand2,
+                            uint64_t n, uint64_t modulus, uint64_t input_mod_factor, ntt_stream_t stream);
+ntt_status eltwise_add_mod(uint64_t* result, const uint64_t* operand1, const uint64_t* operand2,
+                           uint64_t n, uint64_t modulus, ntt_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * RNS batches (Section 5: a polynomial modulo Q = q_0 ... q_{L-1} is held as
+ * L residue polynomials, one per word-sized prime, processed limb by limb).
+ * Layout: num_polys polynomials, each num_limbs limbs of N coefficients,
+ * limb-major and contiguous: element (p, l, i) is at [(p*num_limbs + l)*N + i].
+ * `moduli` is a HOST array of num_limbs primes (limb l uses moduli[l]; every
+ * prime must satisfy the single-limb conditions for N).  Each call is one
+ * batched launch sequence over all num_polys * num_limbs limbs; semantics per
+ * limb are exactly those of the single-limb calls above.
+ *   num_limbs in [1, NTT_MAX_LIMBS], num_polys >= 1.
+ */
+ntt_status ntt_forward_rns(uint64_t* result, const uint64_t* operand, uint64_t N,
+                           const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
+                           uint64_t input_mod_factor, uint64_t output_mod_factor, ntt_stream_t stream);
+ntt_status ntt_inverse_rns(uint64_t* result, const uint64_t* operand, uint64_t N,
+                           const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
+                           uint64_t input_mod_factor, uint64_t output_mod_factor, ntt_stream_t stream);
+ntt_status eltwise_mult_mod_rns(uint64_t* result, const uint64_t* operand1, const uint64_t* operand2,
+                                uint64_t N, const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
+                                uint64_t input_mod_factor, ntt_stream_t stream);
+ntt_status eltwise_add_mod_rns(uint64_t* result, const uint64_t* operand1, const uint64_t* operand2,
+                               uint64_t N, const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
+                               ntt_stream_t stream);
+
+/* Negacyclic product of RNS polynomials: result = a * b mod (X^N + 1, q_l)
+ * per limb (Section 2 vector-vector multiplication), computed as in the
+ * Section 4 input_mod_factor listing: forward(a, 1 -> 4), forward(b, 1 -> 4),
+ * element-wise multiply with input factor 4, inverse (1 -> 1).  The last pass
+ * of the forward transform of b is fused with the element-wise multiply.
+ *   a, b       canonical inputs in [0, q_l), left unchanged
+ *   result     canonical output; may equal a (in place), must not overlap b
+ *   workspace  device buffer of num_polys * num_limbs * N words holding the
+ *              intermediate passes of forward(b); may be NULL when N <= 2^13
+ *              (one on-chip pass per transform), required otherwise
+ *              (NTT_EINVAL_POINTER).  Must not overlap a, b or result. */
+ntt_status poly_mul_rns(uint64_t* result, const uint64_t* a, const uint64_t* b, uint64_t N,
+                        const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
+                        uint64_t* workspace, ntt_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NTT_HIP_H */

@@ -1,0 +1,194 @@
+"""Python binding of the MI355X negacyclic NTT library (C ABI in include/ntt_hip.h).
+
+Argument marshalling only: every operation runs in the HIP kernels of
+libntt_hip.so.  Tensors must be contiguous torch tensors of dtype uint64 (or
+int64 holding the same bits) on a ROCm device; they provide device memory, and
+torch's current stream (or an explicit one) orders the work.  There is no CPU
+fallback: if the library is not built, importing this package raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libntt_hip.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        "libntt_hip.so is not built (expected at %s); run `python paper_2103_16400_amd/build.py` "
+        "or __graft_entry__.build()" % LIB_PATH)
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_U64 = ctypes.c_uint64
+_P = ctypes.c_void_p
+_ST = ctypes.c_int
+
+_SIGS = {
+    "ntt_status_string": (ctypes.c_char_p, [_ST]),
+    "ntt_shutdown": (_ST, []),
+    "ntt_plan_create": (_ST, [ctypes.POINTER(_P), _U64, _U64, _U64]),
+    "ntt_plan_destroy": (_ST, [_P]),
+    "ntt_plan_root": (_U64, [_P]),
+    "ntt_forward": (_ST, [_P, _P, _U64, _U64, _U64, _U64, _P]),
+    "ntt_inverse": (_ST, [_P, _P, _U64, _U64, _U64, _U64, _P]),
+    "ntt_forward_plan": (_ST, [_P, _P, _P, _U64, _U64, _P]),
+    "ntt_inverse_plan": (_ST, [_P, _P, _P, _U64, _U64, _P]),
+    "eltwise_mult_mod": (_ST, [_P, _P, _P, _U64, _U64, _U64, _P]),
+    "eltwise_add_mod": (_ST, [_P, _P, _P, _U64, _U64, _P]),
+    "ntt_forward_rns": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _U64, _P]),
+    "ntt_inverse_rns": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _U64, _P]),
+    "eltwise_mult_mod_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _U64, _P]),
+    "eltwise_add_mod_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P]),
+    "poly_mul_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P, _P]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+# status codes (include/ntt_hip.h)
+NTT_OK = 0
+NTT_EINVAL_DEGREE = -1
+NTT_EINVAL_MODULUS = -2
+NTT_EINVAL_ROOT = -3
+NTT_EINVAL_FACTOR = -4
+NTT_EINVAL_POINTER = -5
+NTT_EALIAS = -6
+NTT_EINVAL_COUNT = -7
+NTT_EDEVICE = -8
+NTT_ENOMEM = -9
+NTT_ENOTFOUND = -10
+NTT_EBUSY = -11
+
+
+class NttError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__("%s failed: %s (%d)" % (what, status_string(status), status))
+
+
+def status_string(status: int) -> str:
+    return _lib.ntt_status_string(status).decode()
+
+
+def lib():
+    """The loaded ctypes library (for callers that pass raw pointers)."""
+    return _lib
+
+
+def _check(status: int, what: str):
+    if status != NTT_OK:
+        raise NttError(status, what)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.dtype not in (torch.uint64, torch.int64):
+        raise TypeError("expected a uint64 (or int64) tensor, got %s" % t.dtype)
+    if not t.is_cuda:
+        raise ValueError("tensor must be on a ROCm device")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _moduli(moduli):
+    arr = (_U64 * len(moduli))(*[int(q) for q in moduli])
+    return arr, len(moduli)
+
+
+class Plan:
+    """Device-resident tables for one (N, q, psi) (the paper's NTT object)."""
+
+    def __init__(self, N: int, q: int, root_of_unity: int = 0):
+        h = _P()
+        _check(_lib.ntt_plan_create(ctypes.byref(h), N, q, root_of_unity), "ntt_plan_create")
+        self._h = h
+        self.N, self.q = N, q
+        self.root = int(_lib.ntt_plan_root(h))
+
+    def close(self):
+        if self._h:
+            _lib.ntt_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, result, operand, input_mod_factor=1, output_mod_factor=1, stream=None):
+        _check(_lib.ntt_forward_plan(self._h, _ptr(result), _ptr(operand), input_mod_factor,
+                                     output_mod_factor, _stream(stream)), "ntt_forward_plan")
+
+    def inverse(self, result, operand, input_mod_factor=1, output_mod_factor=1, stream=None):
+        _check(_lib.ntt_inverse_plan(self._h, _ptr(result), _ptr(operand), input_mod_factor,
+                                     output_mod_factor, _stream(stream)), "ntt_inverse_plan")
+
+
+def ntt_forward(result, operand, N, q, input_mod_factor=1, output_mod_factor=1, stream=None):
+    _check(_lib.ntt_forward(_ptr(result), _ptr(operand), N, q, input_mod_factor, output_mod_factor,
+                            _stream(stream)), "ntt_forward")
+
+
+def ntt_inverse(result, operand, N, q, input_mod_factor=1, output_mod_factor=1, stream=None):
+    _check(_lib.ntt_inverse(_ptr(result), _ptr(operand), N, q, input_mod_factor, output_mod_factor,
+                            _stream(stream)), "ntt_inverse")
+
+
+def eltwise_mult_mod(result, operand1, operand2, n, modulus, input_mod_factor=1, stream=None):
+    _check(_lib.eltwise_mult_mod(_ptr(result), _ptr(operand1), _ptr(operand2), n, modulus, input_mod_factor,
+                                 _stream(stream)), "eltwise_mult_mod")
+
+
+def eltwise_add_mod(result, operand1, operand2, n, modulus, stream=None):
+    _check(_lib.eltwise_add_mod(_ptr(result), _ptr(operand1), _ptr(operand2), n, modulus, _stream(stream)),
+           "eltwise_add_mod")
+
+
+def ntt_forward_rns(result, operand, N, moduli, num_polys, input_mod_factor=1, output_mod_factor=1, stream=None):
+    m, L = _moduli(moduli)
+    _check(_lib.ntt_forward_rns(_ptr(result), _ptr(operand), N, m, L, num_polys, input_mod_factor,
+                                output_mod_factor, _stream(stream)), "ntt_forward_rns")
+
+
+def ntt_inverse_rns(result, operand, N, moduli, num_polys, input_mod_factor=1, output_mod_factor=1, stream=None):
+    m, L = _moduli(moduli)
+    _check(_lib.ntt_inverse_rns(_ptr(result), _ptr(operand), N, m, L, num_polys, input_mod_factor,
+                                output_mod_factor, _stream(stream)), "ntt_inverse_rns")
+
+
+def eltwise_mult_mod_rns(result, operand1, operand2, N, moduli, num_polys, input_mod_factor=1, stream=None):
+    m, L = _moduli(moduli)
+    _check(_lib.eltwise_mult_mod_rns(_ptr(result), _ptr(operand1), _ptr(operand2), N, m, L, num_polys,
+                                     input_mod_factor, _stream(stream)), "eltwise_mult_mod_rns")
+
+
+def eltwise_add_mod_rns(result, operand1, operand2, N, moduli, num_polys, stream=None):
+    m, L = _moduli(moduli)
+    _check(_lib.eltwise_add_mod_rns(_ptr(result), _ptr(operand1), _ptr(operand2), N, m, L, num_polys,
+                                    _stream(stream)), "eltwise_add_mod_rns")
+
+
+def poly_mul_rns(result, a, b, N, moduli, num_polys, workspace=None, stream=None):
+    m, L = _moduli(moduli)
+    _check(_lib.poly_mul_rns(_ptr(result), _ptr(a), _ptr(b), N, m, L, num_polys, _ptr(workspace),
+                             _stream(stream)), "poly_mul_rns")
+
+
+def shutdown():
+    _check(_lib.ntt_shutdown(), "ntt_shutdown")

@@ -1,0 +1,238 @@
+// extern "C" entry points: argument validation, plan lookup, launches.
+#include <hip/hip_runtime.h>
+#include <vector>
+
+#include "internal.h"
+
+using namespace nttamd;
+
+namespace {
+
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+  return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+// An output may equal an input exactly (in place) but not overlap it otherwise.
+ntt_status check_alias(const void* out, const void* in, size_t bytes) {
+  if (out == in) return NTT_OK;
+  return overlaps(out, bytes, in, bytes) ? NTT_EALIAS : NTT_OK;
+}
+
+ntt_status check_fwd_factors(uint64_t in_f, uint64_t out_f) {
+  if (!(in_f == 1 || in_f == 2 || in_f == 4)) return NTT_EINVAL_FACTOR;
+  if (!(out_f == 1 || out_f == 4)) return NTT_EINVAL_FACTOR;
+  return NTT_OK;
+}
+ntt_status check_inv_factors(uint64_t in_f, uint64_t out_f) {
+  if (!(in_f == 1 || in_f == 2)) return NTT_EINVAL_FACTOR;
+  if (!(out_f == 1 || out_f == 2)) return NTT_EINVAL_FACTOR;
+  return NTT_OK;
+}
+
+// q in [2, 2^62) and f * q < 2^63 (Algorithm 8 requirements).
+ntt_status check_mult_modulus(uint64_t q, uint64_t in_f) {
+  if (!(in_f == 1 || in_f == 2 || in_f == 4)) return NTT_EINVAL_FACTOR;
+  if (q < 2 || q >= (1ull << 62)) return NTT_EINVAL_MODULUS;
+  if ((unsigned __int128)q * in_f >= ((unsigned __int128)1 << 63)) return NTT_EINVAL_MODULUS;
+  return NTT_OK;
+}
+// q in [2, 2^63 - 1] (EltwiseAddMod contract).
+ntt_status check_add_modulus(uint64_t q) {
+  if (q < 2 || q > (1ull << 63) - 1) return NTT_EINVAL_MODULUS;
+  return NTT_OK;
+}
+
+ntt_status rns_plans(uint64_t N, const uint64_t* moduli, uint64_t L, std::vector<const ntt_plan*>& plans) {
+  if (!moduli) return NTT_EINVAL_POINTER;
+  if (L == 0 || L > NTT_MAX_LIMBS) return NTT_EINVAL_COUNT;
+  ntt_status st = validate_degree(N);
+  if (st) return st;
+  plans.resize(L);
+  for (uint64_t i = 0; i < L; ++i) {
+    st = cached_plan(N, moduli[i], &plans[i]);
+    if (st) return st;
+  }
+  return NTT_OK;
+}
+
+ntt_status ntt_rns(bool fwd, uint64_t* result, const uint64_t* operand, const uint64_t* mul, uint64_t* tmp,
+                   uint64_t N, const uint64_t* moduli, uint64_t L, uint64_t B, uint64_t in_f, uint64_t out_f,
+                   ntt_stream_t stream) {
+  if (!result || !operand) return NTT_EINVAL_POINTER;
+  ntt_status st = fwd ? check_fwd_factors(in_f, out_f) : check_inv_factors(in_f, out_f);
+  if (st) return st;
+  if (B == 0 || L == 0) return NTT_EINVAL_COUNT;
+  st = validate_degree(N);
+  if (st) return st;
+  if (B > (1ull << 40) / (L * N)) return NTT_EINVAL_COUNT;
+  const size_t bytes = (size_t)(B * L * N * sizeof(uint64_t));
+  st = check_alias(result, operand, bytes);
+  if (st) return st;
+  std::vector<const ntt_plan*> plans;
+  st = rns_plans(N, moduli, L, plans);
+  if (st) return st;
+  NttLaunch l{result, operand, mul, tmp, plans.data(), (uint32_t)L, B, (uint32_t)in_f, (uint32_t)out_f,
+              (hipStream_t)stream};
+  return fwd ? launch_forward(l) : launch_inverse(l);
+}
+
+ntt_status elt_rns(bool mult, uint64_t* result, const uint64_t* a, const uint64_t* b, uint64_t N,
+                   const uint64_t* moduli, uint64_t L, uint64_t B, uint64_t in_f, ntt_stream_t stream) {
+  if (!result || !a || !b || !moduli) return NTT_EINVAL_POINTER;
+  if (N == 0 || B == 0 || L == 0 || L > NTT_MAX_LIMBS) return NTT_EINVAL_COUNT;
+  if (B > (1ull << 40) / (L * N)) return NTT_EINVAL_COUNT;
+  for (uint64_t i = 0; i < L; ++i) {
+    ntt_status st = mult ? check_mult_modulus(moduli[i], in_f) : check_add_modulus(moduli[i]);
+    if (st) return st;
+  }
+  const size_t bytes = (size_t)(B * L * N * sizeof(uint64_t));
+  ntt_status st = check_alias(result, a, bytes);
+  if (st) return st;
+  st = check_alias(result, b, bytes);
+  if (st) return st;
+  EltLaunch l{result, a, b, N, moduli, (uint32_t)L, B, (uint32_t)in_f, (hipStream_t)stream};
+  return mult ? launch_eltwise_mult(l) : launch_eltwise_add(l);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ntt_status_string(ntt_status s) {
+  switch (s) {
+    case NTT_OK: return "ok";
+    case NTT_EINVAL_DEGREE: return "invalid degree: N must be a power of two in [2, 2^17]";
+    case NTT_EINVAL_MODULUS: return "invalid modulus: q must be prime, q = 1 mod 2N and within the call's range";
+    case NTT_EINVAL_ROOT: return "invalid root of unity: psi^N must be -1 mod q";
+    case NTT_EINVAL_FACTOR: return "invalid input/output modulus factor";
+    case NTT_EINVAL_POINTER: return "null pointer argument";
+    case NTT_EALIAS: return "output partially overlaps an input";
+    case NTT_EINVAL_COUNT: return "invalid length, limb count or polynomial count";
+    case NTT_EDEVICE: return "HIP runtime error";
+    case NTT_ENOMEM: return "out of memory";
+    case NTT_ENOTFOUND: return "not found";
+    case NTT_EBUSY: return "busy: admission refused";
+    default: return "unknown status";
+  }
+}
+
+ntt_status ntt_shutdown(void) {
+  clear_plan_cache();
+  return NTT_OK;
+}
+
+ntt_status ntt_plan_create(ntt_plan** plan, uint64_t N, uint64_t q, uint64_t root_of_unity) {
+  return build_plan(plan, N, q, root_of_unity);
+}
+
+ntt_status ntt_plan_destroy(ntt_plan* plan) {
+  if (!plan) return NTT_EINVAL_POINTER;
+  (void)hipFree(plan->dev);
+  delete plan;
+  return NTT_OK;
+}
+
+uint64_t ntt_plan_root(const ntt_plan* plan) { return plan ? plan->psi : 0; }
+
+static ntt_status single_plan_call(bool fwd, const ntt_plan* plan, uint64_t* result, const uint64_t* operand,
+                                   uint64_t in_f, uint64_t out_f, ntt_stream_t stream) {
+  if (!plan || !result || !operand) return NTT_EINVAL_POINTER;
+  ntt_status st = fwd ? check_fwd_factors(in_f, out_f) : check_inv_factors(in_f, out_f);
+  if (st) return st;
+  st = check_alias(result, operand, plan->N * sizeof(uint64_t));
+  if (st) return st;
+  const ntt_plan* plans[1] = {plan};
+  NttLaunch l{result, operand, nullptr, nullptr, plans, 1, 1, (uint32_t)in_f, (uint32_t)out_f, (hipStream_t)stream};
+  return fwd ? launch_forward(l) : launch_inverse(l);
+}
+
+ntt_status ntt_forward_plan(const ntt_plan* plan, uint64_t* result, const uint64_t* operand,
+                            uint64_t input_mod_factor, uint64_t output_mod_factor, ntt_stream_t stream) {
+  return single_plan_call(true, plan, result, operand, input_mod_factor, output_mod_factor, stream);
+}
+
+ntt_status ntt_inverse_plan(const ntt_plan* plan, uint64_t* result, const uint64_t* operand,
+                            uint64_t input_mod_factor, uint64_t output_mod_factor, ntt_stream_t stream) {
+  return single_plan_call(false, plan, result, operand, input_mod_factor, output_mod_factor, stream);
+}
+
+ntt_status ntt_forward(uint64_t* result, const uint64_t* operand, uint64_t N, uint64_t q,
+                       uint64_t input_mod_factor, uint64_t output_mod_factor, ntt_stream_t stream) {
+  return ntt_rns(true, result, operand, nullptr, nullptr, N, &q, 1, 1, input_mod_factor, output_mod_factor, stream);
+}
+
+ntt_status ntt_inverse(uint64_t* result, const uint64_t* operand, uint64_t N, uint64_t q,
+                       uint64_t input_mod_factor, uint64_t output_mod_factor, ntt_stream_t stream) {
+  return ntt_rns(false, result, operand, nullptr, nullptr, N, &q, 1, 1, input_mod_factor, output_mod_factor, stream);
+}
+
+ntt_status eltwise_mult_mod(uint64_t* result, const uint64_t* operand1, const uint64_t* operand2, uint64_t n,
+                            uint64_t modulus, uint64_t input_mod_factor, ntt_stream_t stream) {
+  return elt_rns(true, result, operand1, operand2, n, &modulus, 1, 1, input_mod_factor, stream);
+}
+
+ntt_status eltwise_add_mod(uint64_t* result, const uint64_t* operand1, const uint64_t* operand2, uint64_t n,
+                           uint64_t modulus, ntt_stream_t stream) {
+  return elt_rns(false, result, operand1, operand2, n, &modulus, 1, 1, 1, stream);
+}
+
+ntt_status ntt_forward_rns(uint64_t* result, const uint64_t* operand, uint64_t N, const uint64_t* moduli,
+                           uint64_t num_limbs, uint64_t num_polys, uint64_t input_mod_factor,
+                           uint64_t output_mod_factor, ntt_stream_t stream) {
+  return ntt_rns(true, result, operand, nullptr, nullptr, N, moduli, num_limbs, num_polys, input_mod_factor,
+                 output_mod_factor, stream);
+}
+
+ntt_status ntt_inverse_rns(uint64_t* result, const uint64_t* operand, uint64_t N, const uint64_t* moduli,
+                           uint64_t num_limbs, uint64_t num_polys, uint64_t input_mod_factor,
+                           uint64_t output_mod_factor, ntt_stream_t stream) {
+  return ntt_rns(false, result, operand, nullptr, nullptr, N, moduli, num_limbs, num_polys, input_mod_factor,
+                 output_mod_factor, stream);
+}
+
+ntt_status eltwise_mult_mod_rns(uint64_t* result, const uint64_t* operand1, const uint64_t* operand2, uint64_t N,
+                                const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
+                                uint64_t input_mod_factor, ntt_stream_t stream) {
+  return elt_rns(true, result, operand1, operand2, N, moduli, num_limbs, num_polys, input_mod_factor, stream);
+}
+
+ntt_status eltwise_add_mod_rns(uint64_t* result, const uint64_t* operand1, const uint64_t* operand2, uint64_t N,
+                               const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
+                               ntt_stream_t stream) {
+  return elt_rns(false, result, operand1, operand2, N, moduli, num_limbs, num_polys, 1, stream);
+}
+
+ntt_status poly_mul_rns(uint64_t* result, const uint64_t* a, const uint64_t* b, uint64_t N,
+                        const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys, uint64_t* workspace,
+                        ntt_stream_t stream) {
+  if (!result || !a || !b) return NTT_EINVAL_POINTER;
+  if (num_limbs == 0 || num_polys == 0) return NTT_EINVAL_COUNT;
+  ntt_status st = validate_degree(N);
+  if (st) return st;
+  if (num_polys > (1ull << 40) / (num_limbs * N)) return NTT_EINVAL_COUNT;
+  const size_t bytes = (size_t)(num_polys * num_limbs * N * sizeof(uint64_t));
+  if (overlaps(result, bytes, b, bytes)) return NTT_EALIAS;
+  st = check_alias(result, a, bytes);
+  if (st) return st;
+  int logN = 0;
+  while ((1ull << logN) < N) ++logN;
+  const bool one_pass = pass_count(logN) == 1;
+  if (!one_pass) {
+    if (!workspace) return NTT_EINVAL_POINTER;
+    if (overlaps(workspace, bytes, a, bytes) || overlaps(workspace, bytes, b, bytes) ||
+        overlaps(workspace, bytes, result, bytes))
+      return NTT_EALIAS;
+  }
+  // result <- NTT(a) in [0, 4q)
+  st = ntt_rns(true, result, a, nullptr, nullptr, N, moduli, num_limbs, num_polys, 1, 4, stream);
+  if (st) return st;
+  // result <- NTT(b) (.) result, canonical (last pass of forward(b) fused with the multiply, factor 4)
+  st = ntt_rns(true, result, b, result, one_pass ? nullptr : workspace, N, moduli, num_limbs, num_polys, 1, 4,
+               stream);
+  if (st) return st;
+  // result <- InvNTT(result), canonical
+  return ntt_rns(false, result, result, nullptr, nullptr, N, moduli, num_limbs, num_polys, 1, 1, stream);
+}
+
+}  // extern "C"

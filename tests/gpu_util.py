@@ -1,0 +1,26 @@
+"""Helpers for the GPU parity tests: host numpy uint64 <-> device tensors."""
+import numpy as np
+
+
+def to_dev(a: np.ndarray):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).to("cuda:0")
+
+
+def from_dev(t) -> np.ndarray:
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint64)
+
+
+def empty_dev(n: int):
+    import torch
+    return torch.empty(n, dtype=torch.int64, device="cuda:0")
+
+
+def have_gpu() -> bool:
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False

@@ -1,0 +1,295 @@
+"""GPU parity: every HIP result is compared with the CPU oracle on the same
+seeded inputs.  Integer work, so the bar is bit-exact: canonical outputs equal
+the oracle; lazy outputs (output_mod_factor 4 forward, 2 inverse) lie in
+[0, f q) and reduce to the oracle's value mod q; forward lazy outputs also equal
+the Harvey model bit for bit (the kernels keep Algorithm 4's arithmetic)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from synthetic import lazy_mod, uniform_mod, unit_seed
+from gpu_util import empty_dev, from_dev, have_gpu, to_dev
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not have_gpu(), reason="needs a ROCm GPU")]
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PRIMES = json.load(open(os.path.join(ROOT, "tests", "golden", "primes.json")))
+
+
+@pytest.fixture(scope="module")
+def nt():
+    import paper_2103_16400_amd as nt
+    return nt
+
+
+def _prime(logN, which=0, bits=50):
+    return oracle.find_primes(bits, 2 << logN, which + 1)[which]
+
+
+def _edge(Q, k=0):
+    return PRIMES["edge"]["by_bits"][str(Q)][k]
+
+
+def _fwd_check(out, a, q, psi, out_f, full=True, idx=None):
+    assert np.all(out < np.uint64(out_f * q)), "output outside [0, out_f q)"
+    if full:
+        ref = oracle.ntt_forward(a, q, psi)
+        assert np.array_equal(out % np.uint64(q), ref)
+        if out_f == 4:
+            assert np.array_equal(out, oracle.harvey_forward(a, q, psi, 4))
+    else:
+        ref = oracle.ntt_forward_at(a, idx, q, psi)
+        assert np.array_equal(out[idx] % np.uint64(q), ref)
+
+
+def _sample_idx(N, seed, k=48):
+    r = uniform_mod(unit_seed(seed, N), k, N).astype(np.uint64)
+    return np.unique(np.concatenate([r, np.array([0, 1, N // 2, N - 1], dtype=np.uint64)]))
+
+
+# ---------------------------------------------------------------- element-wise
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 1024, 4097, (1 << 20) + 3])
+def test_eltwise_add_and_mult(nt, n):
+    for q in [2, 3, 12289, _edge(50), _edge(62, 1), (1 << 62) - 57]:
+        a = uniform_mod(unit_seed(1, n, q), n, q)
+        b = uniform_mod(unit_seed(2, n, q), n, q)
+        da, db, dc = to_dev(a), to_dev(b), empty_dev(n)
+        nt.eltwise_add_mod(dc, da, db, n, q)
+        assert np.array_equal(from_dev(dc), oracle.eltwise_add(a, b, q))
+        nt.eltwise_mult_mod(dc, da, db, n, q, 1)
+        assert np.array_equal(from_dev(dc), oracle.eltwise_mult(a, b, q))
+    q = (1 << 63) - 25
+    a = uniform_mod(unit_seed(3, n), n, q)
+    b = uniform_mod(unit_seed(4, n), n, q)
+    dc = empty_dev(n)
+    nt.eltwise_add_mod(dc, to_dev(a), to_dev(b), n, q)
+    assert np.array_equal(from_dev(dc), oracle.eltwise_add(a, b, q))
+
+
+@pytest.mark.parametrize("Q", list(range(30, 63)))
+def test_eltwise_mult_barrett_edges(nt, Q):
+    """Smallest Q-bit primes (Barrett's quotient estimate is weakest just above
+    2^(Q-1)), all input factors, uniform operands and operands near f q - 1."""
+    n = 1 << 14
+    for q in PRIMES["edge"]["by_bits"][str(Q)]:
+        for f in (1, 2, 4):
+            if f * q >= (1 << 63):
+                continue
+            a = lazy_mod(unit_seed(5, Q, q, f), n, q, f)
+            b = lazy_mod(unit_seed(6, Q, q, f), n, q, f)
+            top = np.uint64(f * q - 1)
+            a[: n // 8] = top - (a[: n // 8] % np.uint64(1024))
+            b[: n // 16] = top
+            dc = empty_dev(n)
+            nt.eltwise_mult_mod(dc, to_dev(a), to_dev(b), n, q, f)
+            assert np.array_equal(from_dev(dc), oracle.eltwise_mult(a, b, q)), (q, f)
+
+
+def test_eltwise_in_place_and_unaligned(nt):
+    q = _edge(55)
+    n = 1001
+    a = uniform_mod(unit_seed(7), n + 1, q)
+    b = uniform_mod(unit_seed(8), n + 1, q)
+    da, db = to_dev(a), to_dev(b)
+    # unaligned views (offset by one word) take the scalar path
+    dc = empty_dev(n + 1)
+    nt.eltwise_mult_mod(dc[1:], da[1:], db[1:], n, q, 1)
+    assert np.array_equal(from_dev(dc)[1:], oracle.eltwise_mult(a[1:], b[1:], q))
+    nt.eltwise_add_mod(da, da, db, n + 1, q)          # in place
+    assert np.array_equal(from_dev(da), oracle.eltwise_add(a, b, q))
+
+
+# ---------------------------------------------------------------- single-limb NTT
+
+@pytest.mark.parametrize("logN", list(range(1, 14)))
+def test_forward_inverse_small(nt, logN):
+    N = 1 << logN
+    for q in [_prime(logN, 0, 50), _prime(logN, 0, 62), _prime(logN, 1, 40)]:
+        psi = oracle.min_root(N, q)
+        for in_f in (1, 2, 4):
+            a = lazy_mod(unit_seed(10, logN, q, in_f), N, q, in_f)
+            da = to_dev(a)
+            for out_f in (1, 4):
+                dout = empty_dev(N)
+                nt.ntt_forward(dout, da, N, q, in_f, out_f)
+                _fwd_check(from_dev(dout), a, q, psi, out_f)
+        A = oracle.ntt_forward(uniform_mod(unit_seed(11, logN, q), N, q), q, psi)
+        for in_f in (1, 2):
+            Ain = lazy_mod(unit_seed(12, logN, q, in_f), N, q, in_f)
+            ref = oracle.ntt_inverse(Ain, q, psi)
+            dA = to_dev(Ain)
+            for out_f in (1, 2):
+                dout = empty_dev(N)
+                nt.ntt_inverse(dout, dA, N, q, in_f, out_f)
+                out = from_dev(dout)
+                assert np.all(out < np.uint64(out_f * q))
+                assert np.array_equal(out % np.uint64(q), ref)
+        # round trip in place
+        a = uniform_mod(unit_seed(13, logN, q), N, q)
+        d = to_dev(a)
+        nt.ntt_forward(d, d, N, q, 1, 4)
+        d2 = to_dev(from_dev(d) % np.uint64(q))
+        nt.ntt_inverse(d2, d2, N, q, 1, 1)
+        assert np.array_equal(from_dev(d2), a)
+
+
+@pytest.mark.parametrize("logN", [14, 15, 16, 17])
+def test_forward_inverse_multipass(nt, logN):
+    N = 1 << logN
+    for q in [_prime(logN, 0, 50), _prime(logN, 0, 61)]:
+        psi = oracle.min_root(N, q)
+        idx = _sample_idx(N, logN)
+        for in_f, out_f in [(1, 1), (4, 4), (2, 4)]:
+            a = lazy_mod(unit_seed(20, logN, q, in_f), N, q, in_f)
+            dout = empty_dev(N)
+            nt.ntt_forward(dout, to_dev(a), N, q, in_f, out_f)
+            out = from_dev(dout)
+            _fwd_check(out, a, q, psi, out_f, full=False, idx=idx)
+            if out_f == 4:   # the whole lazy output equals the Harvey model (O(N log N) on the CPU)
+                assert np.array_equal(out, oracle.harvey_forward(a, q, psi, 4))
+        for in_f, out_f in [(1, 1), (2, 2)]:
+            A = lazy_mod(unit_seed(21, logN, q, in_f), N, q, in_f)
+            dout = empty_dev(N)
+            nt.ntt_inverse(dout, to_dev(A), N, q, in_f, out_f)
+            out = from_dev(dout)
+            assert np.all(out < np.uint64(out_f * q))
+            assert np.array_equal(out[idx] % np.uint64(q), oracle.ntt_inverse_at(A, idx, q, psi))
+            assert np.array_equal(out % np.uint64(q), oracle.harvey_inverse(A, q, psi, 1))
+        # round trip
+        a = uniform_mod(unit_seed(22, logN, q), N, q)
+        d = to_dev(a)
+        nt.ntt_forward(d, d, N, q, 1, 1)
+        nt.ntt_inverse(d, d, N, q, 1, 1)
+        assert np.array_equal(from_dev(d), a)
+
+
+def test_explicit_root_plans(nt):
+    for logN in [3, 10, 14]:
+        N = 1 << logN
+        q = _prime(logN, 2, 58)
+        psi_min = oracle.min_root(N, q)
+        psi = pow(psi_min, 2 * 5 + 1, q)       # another primitive 2N-th root
+        plan = nt.Plan(N, q, psi)
+        assert plan.root == psi
+        assert nt.Plan(N, q).root == psi_min
+        a = uniform_mod(unit_seed(30, logN), N, q)
+        d, o = to_dev(a), empty_dev(N)
+        plan.forward(o, d, 1, 1)
+        out = from_dev(o)
+        if N <= 4096:
+            assert np.array_equal(out, oracle.ntt_forward(a, q, psi))
+        else:
+            idx = _sample_idx(N, 31)
+            assert np.array_equal(out[idx], oracle.ntt_forward_at(a, idx, q, psi))
+        plan.inverse(o, o, 1, 1)
+        assert np.array_equal(from_dev(o), a)
+        plan.close()
+    with pytest.raises(nt.NttError) as e:
+        nt.Plan(8, 17, 2)          # 2^8 = 1 mod 17, not -1: not a primitive 16th root
+    assert e.value.status == nt.NTT_EINVAL_ROOT
+    with pytest.raises(nt.NttError) as e:
+        nt.Plan(8, 17 * 97 + 0, 0)
+    assert e.value.status == nt.NTT_EINVAL_MODULUS
+
+
+def test_composite_modulus_rejected(nt):
+    N = 1024
+    q = 2049 * 2048 + 1           # = 1 mod 2048
+    while oracle.is_prime(q):
+        q += 2048
+    d = empty_dev(N)
+    with pytest.raises(nt.NttError) as e:
+        nt.ntt_forward(d, d, N, q)
+    assert e.value.status == nt.NTT_EINVAL_MODULUS
+
+
+# ---------------------------------------------------------------- RNS batches
+
+def _rns_inputs(tag, N, moduli, B, f=1):
+    L = len(moduli)
+    out = np.empty(B * L * N, dtype=np.uint64)
+    for p in range(B):
+        for l, q in enumerate(moduli):
+            out[(p * L + l) * N:(p * L + l + 1) * N] = lazy_mod(unit_seed(tag, p, l, q), N, q, f)
+    return out
+
+
+@pytest.mark.parametrize("key,B", [("rns_16384", 2), ("large_65536", 1)])
+def test_rns_forward_inverse(nt, key, B):
+    N = PRIMES[key]["N"]
+    moduli = PRIMES[key]["moduli"]
+    L = len(moduli)
+    a = _rns_inputs(40, N, moduli, B)
+    d = to_dev(a)
+    o = empty_dev(a.size)
+    nt.ntt_forward_rns(o, d, N, moduli, B, 1, 4)
+    out = from_dev(o)
+    idx = _sample_idx(N, 41, 16)
+    for p in range(B):
+        for l, q in enumerate(moduli):
+            seg = out[(p * L + l) * N:(p * L + l + 1) * N]
+            src = a[(p * L + l) * N:(p * L + l + 1) * N]
+            assert np.all(seg < np.uint64(4 * q))
+            psi = PRIMES[key]["psi"][l]
+            assert np.array_equal(seg[idx] % np.uint64(q), oracle.ntt_forward_at(src, idx, q, psi))
+            if l in (0, L - 1):
+                assert np.array_equal(seg, oracle.harvey_forward(src, q, psi, 4))
+    # lazy [0, 4q) is not a legal inverse input: reduce on the host first
+    canon = to_dev(np.concatenate([
+        out[(p * L + l) * N:(p * L + l + 1) * N] % np.uint64(q)
+        for p in range(B) for l, q in enumerate(moduli)]))
+    nt.ntt_inverse_rns(canon, canon, N, moduli, B, 1, 1)
+    assert np.array_equal(from_dev(canon), a)
+
+
+def test_rns_eltwise(nt):
+    N = 4096
+    moduli = PRIMES["serving"]["moduli"][:12]
+    B = 3
+    a = _rns_inputs(50, N, moduli, B, 4)
+    b = _rns_inputs(51, N, moduli, B, 4)
+    c = empty_dev(a.size)
+    nt.eltwise_mult_mod_rns(c, to_dev(a), to_dev(b), N, moduli, B, 4)
+    out = from_dev(c)
+    L = len(moduli)
+    for p in range(B):
+        for l, q in enumerate(moduli):
+            s = slice((p * L + l) * N, (p * L + l + 1) * N)
+            assert np.array_equal(out[s], oracle.eltwise_mult(a[s], b[s], q))
+    a1 = _rns_inputs(52, N, moduli, B, 1)
+    b1 = _rns_inputs(53, N, moduli, B, 1)
+    nt.eltwise_add_mod_rns(c, to_dev(a1), to_dev(b1), N, moduli, B)
+    out = from_dev(c)
+    for p in range(B):
+        for l, q in enumerate(moduli):
+            s = slice((p * L + l) * N, (p * L + l + 1) * N)
+            assert np.array_equal(out[s], oracle.eltwise_add(a1[s], b1[s], q))
+
+
+@pytest.mark.parametrize("logN,L,B", [(1, 1, 3), (4, 2, 2), (10, 3, 2), (12, 40, 1), (13, 2, 1), (14, 8, 2),
+                                      (16, 2, 1), (17, 1, 1)])
+def test_poly_mul_rns(nt, logN, L, B):
+    N = 1 << logN
+    moduli = PRIMES["serving"]["moduli"][:L]
+    a = _rns_inputs(60, N, moduli, B)
+    b = _rns_inputs(61, N, moduli, B)
+    c = empty_dev(a.size)
+    ws = empty_dev(a.size)
+    nt.poly_mul_rns(c, to_dev(a), to_dev(b), N, moduli, B, ws)
+    out = from_dev(c)
+    idx = _sample_idx(N, 62, 12)
+    for p in range(B):
+        for l, q in enumerate(moduli):
+            s = slice((p * L + l) * N, (p * L + l + 1) * N)
+            if N <= 1024:
+                assert np.array_equal(out[s], oracle.negacyclic_mul(a[s], b[s], q))
+            else:
+                assert np.array_equal(out[s][idx], oracle.negacyclic_mul_at(a[s], b[s], idx, q))
+    # in place: result == a
+    da = to_dev(a)
+    nt.poly_mul_rns(da, da, to_dev(b), N, moduli, B, ws)
+    assert np.array_equal(from_dev(da), out)
