@@ -13,6 +13,9 @@ namespace nttamd {
 //   [0, 16)                 header, see PlanHeader
 //   [16, 16 + 2N)           forward pairs (W, W') at index k: W = psi^brv(k)
 //   [16 + 2N, 16 + 4N)      inverse pairs at index k: W = psi^-brv(k)
+//   [16 + 4N, 16 + 8N)      (N <= 2^14 only) the same two tables with the
+//                           sub-tables of the finest stages transposed for the
+//                           single-pass kernel, see onchip_perm_top()
 struct PlanHeader {
   uint64_t q, q2, nq, N;      // q, 2q, 2^64 - q, degree
   uint64_t ninv, ninv_p;      // N^{-1} mod q and floor(N^{-1} 2^64 / q)
@@ -21,6 +24,26 @@ struct PlanHeader {
 };
 static_assert(sizeof(PlanHeader) == 16 * 8, "plan header is 16 words");
 constexpr int kPlanHeaderWords = 16;
+
+// Geometry of the single-pass (on-chip) transform, shared by the plan builder
+// and the kernels.  Each thread holds 2^onchip_logr(logN) coefficients.
+constexpr int kMaxOnchipLog = 14;
+__host__ __device__ constexpr int onchip_logr(int logN) { return logN <= 4 ? logN : (logN <= 12 ? 4 : 5); }
+// In the round where every thread owns 2^logr consecutive coefficients, the
+// stage on index bit b (b <= top) reads, for thread t, the consecutive table
+// entries (N >> (b+1)) + t*S + u, u < S = 2^(logr-1-b).  Those sub-tables are
+// stored transposed, entry (N >> (b+1)) + u*(N >> logr) + t, so that the 64
+// lanes of a wave read 1 KiB contiguous per instruction.  Returns top (-1: none).
+__host__ __device__ constexpr int onchip_perm_top(bool fwd, int logN) {
+  const int logr = onchip_logr(logN);
+  int top = logr - 2;
+  if (fwd) {
+    const int nr = (logN + logr - 1) / logr;
+    const int first = logN - 1 - (nr - 1) * logr;   // highest bit handled by the last round
+    if (first < top) top = first;
+  }
+  return top;
+}
 
 }  // namespace nttamd
 

@@ -1,0 +1,100 @@
+// Pieces shared by the NTT kernels: launch arguments, the per-limb plan view,
+// the compile-time round geometry and the output step of the last pass.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <type_traits>
+
+#include "internal.h"
+#include "modarith.h"
+
+namespace nttamd {
+
+constexpr int kMaxPlansPerLaunch = NTT_MAX_LIMBS;
+
+enum : u32 { kFlagLast = 1u, kFlagCanon = 2u, kFlagMul = 4u };
+
+struct PassArgs {
+  u64* out;
+  const u64* in;
+  const u64* mul;                          // fused multiply operand (kFlagMul), same layout as out
+  const u64* plan[kMaxPlansPerLaunch];     // device plan buffers; item y uses plan[y % num_limbs]
+  u32 num_limbs;
+  u32 logN;
+  u32 b0;                                  // lowest index bit of this pass
+  u32 flags;
+  u32 item0;                               // first item of this launch
+};
+
+// ---- round geometry (compile time) ----------------------------------------
+template <bool FWD, int LOGT, int LOGR>
+struct Geo {
+  static constexpr int NR = (LOGT + LOGR - 1) / LOGR;
+  // lowest row bit owned by a thread in round r
+  static constexpr int lo(int r) {
+    return FWD ? ((LOGT - (r + 1) * LOGR) > 0 ? (LOGT - (r + 1) * LOGR) : 0)
+               : ((r * LOGR) < (LOGT - LOGR) ? (r * LOGR) : (LOGT - LOGR));
+  }
+  // first stage bit processed in round r and number of stages
+  static constexpr int first_bit(int r) { return FWD ? (LOGT - 1 - r * LOGR) : (r * LOGR); }
+  static constexpr int nst(int r) {
+    return FWD ? ((LOGT - r * LOGR) < LOGR ? (LOGT - r * LOGR) : LOGR)
+               : ((LOGT - r * LOGR) < LOGR ? (LOGT - r * LOGR) : LOGR);
+  }
+};
+
+struct PlanView {
+  u64 q, q2, nq;
+  u64 ninv, ninv_p, wn, wn_p;
+  u64 bk;
+  u32 qbits;
+  const ulonglong2* tw;     // natural table of this direction
+  const ulonglong2* twp;    // transposed copy for the single-pass kernel (N <= 2^14)
+};
+
+__device__ __forceinline__ PlanView load_plan(const u64* plan, bool fwd, u64 N) {
+  const PlanHeader* h = reinterpret_cast<const PlanHeader*>(plan);
+  PlanView v;
+  v.q = h->q;
+  v.q2 = h->q2;
+  v.nq = h->nq;
+  v.ninv = h->ninv;
+  v.ninv_p = h->ninv_p;
+  v.wn = h->wn;
+  v.wn_p = h->wn_p;
+  v.bk = h->barrett_k;
+  v.qbits = (u32)h->qbits;
+  v.tw = reinterpret_cast<const ulonglong2*>(plan + kPlanHeaderWords) + (fwd ? 0 : N);
+  v.twp = v.tw + 2 * N;
+  return v;
+}
+
+// Output step of the last pass: final correction, or the fused element-wise
+// product with the multiplier operand (forward transform of a product).
+// Output modes of the last pass, as template arguments of the kernels.
+enum OutMode : int { kOutLazy = 0, kOutCanon = 1, kOutMul = 2 };
+
+template <bool FWD, int MODE>
+__device__ __forceinline__ u64 finish_mode(u64 v, u64 idx, const PassArgs& a, const PlanView& pv) {
+  if (FWD && MODE == kOutMul) return barrett_mulmod<4>(v, a.mul[idx], pv.q, pv.q2, pv.bk, pv.qbits);
+  if (MODE == kOutCanon) return FWD ? reduce4(v, pv.q, pv.q2) : csub(v, pv.q);
+  return v;
+}
+
+// Compiler-level fence: keeps the scheduler from hoisting the next stage's
+// twiddle loads above the current stage (which would blow up register use).
+__device__ __forceinline__ void stage_fence() { __asm__ volatile("" ::: "memory"); }
+
+template <bool FWD>
+__device__ __forceinline__ u64 finish(u64 v, u64 idx, const PassArgs& a, const PlanView& pv) {
+  if (!(a.flags & kFlagLast)) return v;
+  if (FWD) {
+    if (a.flags & kFlagMul) return barrett_mulmod<4>(v, a.mul[idx], pv.q, pv.q2, pv.bk, pv.qbits);
+    if (a.flags & kFlagCanon) return reduce4(v, pv.q, pv.q2);
+    return v;
+  }
+  return (a.flags & kFlagCanon) ? csub(v, pv.q) : v;
+}
+
+ntt_status launch_onchip(const PassArgs& base_args, uint64_t items, bool fwd, hipStream_t stream);
+
+}  // namespace nttamd

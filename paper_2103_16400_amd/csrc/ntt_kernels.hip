@@ -27,52 +27,12 @@
 
 #include "internal.h"
 #include "modarith.h"
+#include "ntt_common.h"
 
 namespace nttamd {
 
-constexpr int kMaxPlansPerLaunch = NTT_MAX_LIMBS;
-
-enum : u32 { kFlagLast = 1u, kFlagCanon = 2u, kFlagMul = 4u };
-
-struct PassArgs {
-  u64* out;
-  const u64* in;
-  const u64* mul;                          // fused multiply operand (kFlagMul), same layout as out
-  const u64* plan[kMaxPlansPerLaunch];     // device plan buffers; item y uses plan[y % num_limbs]
-  u32 num_limbs;
-  u32 logN;
-  u32 b0;                                  // lowest index bit of this pass
-  u32 flags;
-  u32 item0;                               // first item of this launch
-};
-
-// ---- round geometry (compile time) ----------------------------------------
-template <bool FWD, int LOGT, int LOGR>
-struct Geo {
-  static constexpr int NR = (LOGT + LOGR - 1) / LOGR;
-  // lowest row bit owned by a thread in round r
-  static constexpr int lo(int r) {
-    return FWD ? ((LOGT - (r + 1) * LOGR) > 0 ? (LOGT - (r + 1) * LOGR) : 0)
-               : ((r * LOGR) < (LOGT - LOGR) ? (r * LOGR) : (LOGT - LOGR));
-  }
-  // first stage bit processed in round r and number of stages
-  static constexpr int first_bit(int r) { return FWD ? (LOGT - 1 - r * LOGR) : (r * LOGR); }
-  static constexpr int nst(int r) {
-    return FWD ? ((LOGT - r * LOGR) < LOGR ? (LOGT - r * LOGR) : LOGR)
-               : ((LOGT - r * LOGR) < LOGR ? (LOGT - r * LOGR) : LOGR);
-  }
-};
-
 template <int LOGR>
 __device__ __forceinline__ u32 lds_row(u32 rho) { return rho + (rho >> LOGR); }
-
-struct PlanView {
-  u64 q, q2, nq;
-  u64 ninv, ninv_p, wn, wn_p;
-  u64 bk;
-  u32 qbits;
-  const ulonglong2* tw;
-};
 
 template <bool FWD, int LOGT, int LOGR, int LOGC, int LOGH, int R>
 struct Tile {
@@ -149,35 +109,6 @@ struct Tile {
     }
   }
 };
-
-__device__ __forceinline__ PlanView load_plan(const u64* plan, bool fwd, u64 N) {
-  const PlanHeader* h = reinterpret_cast<const PlanHeader*>(plan);
-  PlanView v;
-  v.q = h->q;
-  v.q2 = h->q2;
-  v.nq = h->nq;
-  v.ninv = h->ninv;
-  v.ninv_p = h->ninv_p;
-  v.wn = h->wn;
-  v.wn_p = h->wn_p;
-  v.bk = h->barrett_k;
-  v.qbits = (u32)h->qbits;
-  v.tw = reinterpret_cast<const ulonglong2*>(plan + kPlanHeaderWords) + (fwd ? 0 : N);
-  return v;
-}
-
-// Output step of the last pass: final correction, or the fused element-wise
-// product with the multiplier operand (forward transform of a product).
-template <bool FWD>
-__device__ __forceinline__ u64 finish(u64 v, u64 idx, const PassArgs& a, const PlanView& pv) {
-  if (!(a.flags & kFlagLast)) return v;
-  if (FWD) {
-    if (a.flags & kFlagMul) return barrett_mulmod<4>(v, a.mul[idx], pv.q, pv.q2, pv.bk, pv.qbits);
-    if (a.flags & kFlagCanon) return reduce4(v, pv.q, pv.q2);
-    return v;
-  }
-  return (a.flags & kFlagCanon) ? csub(v, pv.q) : v;
-}
 
 template <bool FWD, int LOGT, int LOGR, int LOGC, int LOGH>
 __global__ void __launch_bounds__(1 << (LOGT + LOGC + LOGH - LOGR))
@@ -278,7 +209,7 @@ static Schedule schedule_for(int logN) {
     case 11: return {1, {{11, 4, 0, 0}}};
     case 12: return {1, {{12, 4, 0, 0}}};
     case 13: return {1, {{13, 4, 0, 0}}};
-    case 14: return {2, {{7, 4, 5, 0}, {7, 4, 0, 5}}};
+    case 14: return {1, {{14, 5, 0, 0}}};
     case 15: return {2, {{8, 4, 4, 0}, {7, 4, 0, 5}}};
     case 16: return {2, {{8, 4, 4, 0}, {8, 4, 0, 4}}};
     case 17: return {2, {{9, 4, 4, 0}, {8, 4, 0, 4}}};
@@ -292,12 +223,7 @@ template <bool FWD>
 static PassKernel pick_kernel(const PassShape& s) {
 #define NTT_CASE(T, R, C, H) \
   if (s.logt == T && s.logr == R && s.logc == C && s.logh == H) return ntt_pass_kernel<FWD, T, R, C, H>;
-  NTT_CASE(1, 1, 0, 0) NTT_CASE(2, 2, 0, 0) NTT_CASE(3, 3, 0, 0) NTT_CASE(4, 4, 0, 0)
-  NTT_CASE(5, 4, 0, 0) NTT_CASE(6, 4, 0, 0) NTT_CASE(7, 4, 0, 0) NTT_CASE(8, 4, 0, 0)
-  NTT_CASE(9, 4, 0, 0) NTT_CASE(10, 4, 0, 0) NTT_CASE(11, 4, 0, 0) NTT_CASE(12, 4, 0, 0)
-  NTT_CASE(13, 4, 0, 0)
-  NTT_CASE(7, 4, 5, 0) NTT_CASE(7, 4, 0, 5) NTT_CASE(8, 4, 4, 0) NTT_CASE(8, 4, 0, 4)
-  NTT_CASE(9, 4, 4, 0)
+  NTT_CASE(7, 4, 0, 5) NTT_CASE(8, 4, 4, 0) NTT_CASE(8, 4, 0, 4) NTT_CASE(9, 4, 4, 0)
 #undef NTT_CASE
   return nullptr;
 }
@@ -323,6 +249,17 @@ static ntt_status launch_passes(const NttLaunch& l, bool fwd) {
   {
     int top = logN;
     for (int i = 0; i < sch.npass; ++i) { top -= sch.pass[i].logt; b0s[i] = top; }
+  }
+  if (sch.npass == 1) {
+    a.in = l.in;
+    a.out = l.out;
+    a.b0 = 0;
+    a.flags = kFlagLast;
+    if (l.out_f == 1) a.flags |= kFlagCanon;
+    if (fwd && l.mul_into) a.flags |= kFlagMul;
+    ntt_status st = launch_onchip(a, items, fwd, l.stream);
+    if (st) return st;
+    return hipGetLastError() == hipSuccess ? NTT_OK : NTT_EDEVICE;
   }
   for (int step = 0; step < sch.npass; ++step) {
     const int i = fwd ? step : (sch.npass - 1 - step);
