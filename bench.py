@@ -2,9 +2,11 @@
 
 One step = one pass of the whole hot path over a batch of RNS polynomials at
 N = 2^14 with 8 limbs of 50-bit primes (q = 1 mod 2N):
-    c   = InvNTT( NTT(a) (.) NTT(b) )         per limb (forward 1->4, forward 1->4
-                                               fused with the modmul, inverse 1->1)
-    acc = acc + c  (mod q)                    element-wise add
+    acc = acc + InvNTT( NTT(a) (.) NTT(b) )   per limb: forward(a) 1->4;
+                                              forward(b) 1->4 fused with the
+                                              element-wise modmul (factor 4);
+                                              inverse 1->1 fused with the
+                                              element-wise add into acc
 The reported value is forward limb-NTTs per second of whole-step throughput
 (2 forward transforms per limb-product; the inverse, the multiply and the add
 run inside the same timed step).  Inputs are seeded synthetic uniform
@@ -97,8 +99,6 @@ def main():
     ws = torch.empty_like(a)
     acc = torch.zeros_like(a)
     stream = torch.cuda.current_stream()
-    # the forward transform of operand a, timed separately inside each step
-    fa = torch.empty_like(a)
 
     ev = []
 
@@ -106,14 +106,12 @@ def main():
         if record:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-        nt.ntt_forward_rns(c, a, N, moduli, B, 1, 4, stream=stream)            # NTT(a), lazy [0, 4q)
+        nt.ntt_forward_rns(c, a, N, moduli, B, 1, 4, stream=stream)             # c = NTT(a), lazy [0, 4q)
         if record:
             e1.record(stream)
             ev.append((e0, e1))
-        nt.ntt_forward_rns(fa, b, N, moduli, B, 1, 4, stream=stream)           # NTT(b) ...
-        nt.eltwise_mult_mod_rns(c, c, fa, N, moduli, B, 4, stream=stream)       # ... (.) NTT(a)
-        nt.ntt_inverse_rns(c, c, N, moduli, B, 1, 1, stream=stream)             # InvNTT
-        nt.eltwise_add_mod_rns(acc, acc, c, N, moduli, B, stream=stream)        # acc += a*b
+        nt.ntt_forward_mul_rns(c, b, c, N, moduli, B, 1, ws, stream=stream)      # c = NTT(b) (.) c
+        nt.ntt_inverse_acc_rns(acc, c, N, moduli, B, 1, ws, stream=stream)      # acc += InvNTT(c)
 
     for _ in range(args.warmup):
         step(False)
@@ -146,11 +144,11 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": "rns_product_n16384_l8", "N": N, "limbs": L, "polys_per_step": B,
-                   "step": "fwd(a) 1->4, fwd(b) 1->4, modmul f=4, inv 1->1, acc add",
+                   "step": "fwd(a) 1->4; fwd(b) 1->4 fused with modmul f=4; inv 1->1 fused with acc add",
                    "forward_ntts_per_step": fwd_per_step},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "forward NTT of %d limbs (ntt_pass_kernel, all passes)" % limbs,
+                     "kernel": "ntt_onchip_kernel<fwd, N=2^14>: forward NTT of %d limbs, one launch" % limbs,
                      "avg_ms": round(fwd_ms, 4), "alg_bytes": alg_bytes},
         "fwd_ntt_rate": round(limbs / (fwd_ms * 1e-3), 1),
         "products_per_s": round(limbs / (wall / args.steps), 1),

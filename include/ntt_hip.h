@@ -179,6 +179,35 @@ ntt_status poly_mul_rns(uint64_t* result, const uint64_t* a, const uint64_t* b, 
                         const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
                         uint64_t* workspace, ntt_stream_t stream);
 
+/* Cross-kernel fusions of the product pipeline (the paper's conclusion names
+ * fusing sequences of its kernels as future work).  Same layouts and limits
+ * as the RNS calls above; `workspace` is a device buffer of
+ * num_polys * num_limbs * N words for the intermediate passes of a multi-pass
+ * transform (N > 2^14); it may be NULL when N <= 2^14.
+ *
+ * ntt_forward_mul_rns: result = NTT(operand) (.) multiplier  (canonical),
+ *   the forward transform (Algorithm 2/4) whose last pass multiplies by the
+ *   multiplier element-wise (Algorithm 8 with input factor 4).  operand in
+ *   [0, f q), f in {1, 2, 4}; multiplier in [0, 4q) (typically a forward
+ *   transform left lazy).  result may equal multiplier or operand.
+ * ntt_inverse_acc_rns: acc = (acc + InvNTT(operand)) mod q, the inverse
+ *   transform (Algorithm 3/5) whose last pass adds into a canonical
+ *   accumulator (EltwiseAddMod).  operand in [0, f q), f in {1, 2}; acc must
+ *   not overlap operand.
+ * poly_mul_acc_rns: acc = acc + a * b  (negacyclic product per limb), as
+ *   forward(a) -> forward-multiply(b) -> inverse-accumulate.  workspace is
+ *   required: num_polys * num_limbs * N words for N <= 2^14, twice that above.
+ */
+ntt_status ntt_forward_mul_rns(uint64_t* result, const uint64_t* operand, const uint64_t* multiplier, uint64_t N,
+                               const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
+                               uint64_t input_mod_factor, uint64_t* workspace, ntt_stream_t stream);
+ntt_status ntt_inverse_acc_rns(uint64_t* acc, const uint64_t* operand, uint64_t N, const uint64_t* moduli,
+                               uint64_t num_limbs, uint64_t num_polys, uint64_t input_mod_factor,
+                               uint64_t* workspace, ntt_stream_t stream);
+ntt_status poly_mul_acc_rns(uint64_t* acc, const uint64_t* a, const uint64_t* b, uint64_t N,
+                            const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
+                            uint64_t* workspace, ntt_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

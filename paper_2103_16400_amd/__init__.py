@@ -42,6 +42,9 @@ _SIGS = {
     "eltwise_mult_mod_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _U64, _P]),
     "eltwise_add_mod_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P]),
     "poly_mul_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P, _P]),
+    "ntt_forward_mul_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _U64, _P, _P]),
+    "ntt_inverse_acc_rns": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _P, _P]),
+    "poly_mul_acc_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -188,6 +191,25 @@ def poly_mul_rns(result, a, b, N, moduli, num_polys, workspace=None, stream=None
     m, L = _moduli(moduli)
     _check(_lib.poly_mul_rns(_ptr(result), _ptr(a), _ptr(b), N, m, L, num_polys, _ptr(workspace),
                              _stream(stream)), "poly_mul_rns")
+
+
+def ntt_forward_mul_rns(result, operand, multiplier, N, moduli, num_polys, input_mod_factor=1, workspace=None,
+                        stream=None):
+    m, L = _moduli(moduli)
+    _check(_lib.ntt_forward_mul_rns(_ptr(result), _ptr(operand), _ptr(multiplier), N, m, L, num_polys,
+                                    input_mod_factor, _ptr(workspace), _stream(stream)), "ntt_forward_mul_rns")
+
+
+def ntt_inverse_acc_rns(acc, operand, N, moduli, num_polys, input_mod_factor=1, workspace=None, stream=None):
+    m, L = _moduli(moduli)
+    _check(_lib.ntt_inverse_acc_rns(_ptr(acc), _ptr(operand), N, m, L, num_polys, input_mod_factor,
+                                    _ptr(workspace), _stream(stream)), "ntt_inverse_acc_rns")
+
+
+def poly_mul_acc_rns(acc, a, b, N, moduli, num_polys, workspace, stream=None):
+    m, L = _moduli(moduli)
+    _check(_lib.poly_mul_acc_rns(_ptr(acc), _ptr(a), _ptr(b), N, m, L, num_polys, _ptr(workspace),
+                                 _stream(stream)), "poly_mul_acc_rns")
 
 
 def shutdown():

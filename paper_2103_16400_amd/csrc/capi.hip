@@ -203,6 +203,55 @@ ntt_status eltwise_add_mod_rns(uint64_t* result, const uint64_t* operand1, const
   return elt_rns(false, result, operand1, operand2, N, moduli, num_limbs, num_polys, 1, stream);
 }
 
+static bool is_one_pass(uint64_t N) {
+  int logN = 0;
+  while ((1ull << logN) < N) ++logN;
+  return pass_count(logN) == 1;
+}
+
+ntt_status ntt_forward_mul_rns(uint64_t* result, const uint64_t* operand, const uint64_t* multiplier, uint64_t N,
+                               const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
+                               uint64_t input_mod_factor, uint64_t* workspace, ntt_stream_t stream) {
+  if (!result || !operand || !multiplier) return NTT_EINVAL_POINTER;
+  if (num_limbs == 0 || num_polys == 0) return NTT_EINVAL_COUNT;
+  ntt_status st = validate_degree(N);
+  if (st) return st;
+  if (num_polys > (1ull << 40) / (num_limbs * N)) return NTT_EINVAL_COUNT;
+  const size_t bytes = (size_t)(num_polys * num_limbs * N * sizeof(uint64_t));
+  st = check_alias(result, multiplier, bytes);
+  if (st) return st;
+  st = check_alias(result, operand, bytes);
+  if (st) return st;
+  const bool one_pass = is_one_pass(N);
+  if (!one_pass) {
+    if (!workspace) return NTT_EINVAL_POINTER;
+    if (overlaps(workspace, bytes, result, bytes) || overlaps(workspace, bytes, operand, bytes) ||
+        overlaps(workspace, bytes, multiplier, bytes))
+      return NTT_EALIAS;
+  }
+  return ntt_rns(true, result, operand, multiplier, one_pass ? nullptr : workspace, N, moduli, num_limbs, num_polys,
+                 input_mod_factor, 4, stream);
+}
+
+ntt_status ntt_inverse_acc_rns(uint64_t* acc, const uint64_t* operand, uint64_t N, const uint64_t* moduli,
+                               uint64_t num_limbs, uint64_t num_polys, uint64_t input_mod_factor, uint64_t* workspace,
+                               ntt_stream_t stream) {
+  if (!acc || !operand) return NTT_EINVAL_POINTER;
+  if (num_limbs == 0 || num_polys == 0) return NTT_EINVAL_COUNT;
+  ntt_status st = validate_degree(N);
+  if (st) return st;
+  if (num_polys > (1ull << 40) / (num_limbs * N)) return NTT_EINVAL_COUNT;
+  const size_t bytes = (size_t)(num_polys * num_limbs * N * sizeof(uint64_t));
+  if (overlaps(acc, bytes, operand, bytes)) return NTT_EALIAS;
+  const bool one_pass = is_one_pass(N);
+  if (!one_pass) {
+    if (!workspace) return NTT_EINVAL_POINTER;
+    if (overlaps(workspace, bytes, acc, bytes) || overlaps(workspace, bytes, operand, bytes)) return NTT_EALIAS;
+  }
+  return ntt_rns(false, acc, operand, acc, one_pass ? nullptr : workspace, N, moduli, num_limbs, num_polys,
+                 input_mod_factor, 1, stream);
+}
+
 ntt_status poly_mul_rns(uint64_t* result, const uint64_t* a, const uint64_t* b, uint64_t N,
                         const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys, uint64_t* workspace,
                         ntt_stream_t stream) {
@@ -215,9 +264,7 @@ ntt_status poly_mul_rns(uint64_t* result, const uint64_t* a, const uint64_t* b, 
   if (overlaps(result, bytes, b, bytes)) return NTT_EALIAS;
   st = check_alias(result, a, bytes);
   if (st) return st;
-  int logN = 0;
-  while ((1ull << logN) < N) ++logN;
-  const bool one_pass = pass_count(logN) == 1;
+  const bool one_pass = is_one_pass(N);
   if (!one_pass) {
     if (!workspace) return NTT_EINVAL_POINTER;
     if (overlaps(workspace, bytes, a, bytes) || overlaps(workspace, bytes, b, bytes) ||
@@ -233,6 +280,32 @@ ntt_status poly_mul_rns(uint64_t* result, const uint64_t* a, const uint64_t* b, 
   if (st) return st;
   // result <- InvNTT(result), canonical
   return ntt_rns(false, result, result, nullptr, nullptr, N, moduli, num_limbs, num_polys, 1, 1, stream);
+}
+
+ntt_status poly_mul_acc_rns(uint64_t* acc, const uint64_t* a, const uint64_t* b, uint64_t N,
+                            const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys, uint64_t* workspace,
+                            ntt_stream_t stream) {
+  if (!acc || !a || !b || !workspace) return NTT_EINVAL_POINTER;
+  if (num_limbs == 0 || num_polys == 0) return NTT_EINVAL_COUNT;
+  ntt_status st = validate_degree(N);
+  if (st) return st;
+  if (num_polys > (1ull << 39) / (num_limbs * N)) return NTT_EINVAL_COUNT;
+  const size_t bytes = (size_t)(num_polys * num_limbs * N * sizeof(uint64_t));
+  const bool one_pass = is_one_pass(N);
+  const size_t wbytes = one_pass ? bytes : 2 * bytes;
+  if (overlaps(acc, bytes, a, bytes) || overlaps(acc, bytes, b, bytes) || overlaps(workspace, wbytes, acc, bytes) ||
+      overlaps(workspace, wbytes, a, bytes) || overlaps(workspace, wbytes, b, bytes))
+    return NTT_EALIAS;
+  uint64_t* prod = workspace;
+  uint64_t* mid = one_pass ? nullptr : workspace + bytes / sizeof(uint64_t);
+  // prod <- NTT(a), lazy
+  st = ntt_rns(true, prod, a, nullptr, nullptr, N, moduli, num_limbs, num_polys, 1, 4, stream);
+  if (st) return st;
+  // prod <- NTT(b) (.) prod, canonical
+  st = ntt_rns(true, prod, b, prod, mid, N, moduli, num_limbs, num_polys, 1, 4, stream);
+  if (st) return st;
+  // acc <- acc + InvNTT(prod); the inverse's intermediate passes run in place on prod
+  return ntt_rns(false, acc, prod, acc, one_pass ? nullptr : prod, N, moduli, num_limbs, num_polys, 1, 1, stream);
 }
 
 }  // extern "C"

@@ -72,7 +72,8 @@ uint64_t barrett_factor(uint64_t q, uint32_t* qbits);
 struct NttLaunch {
   uint64_t* out;
   const uint64_t* in;
-  const uint64_t* mul_into;     // fused forward-and-multiply: out = Barrett(NTT(in), mul_into) (may equal out)
+  const uint64_t* mul_into;     // forward: out = Barrett(NTT(in), mul_into); inverse: out = mul_into + InvNTT(in)
+                                //   (mul_into may equal out)
   uint64_t* tmp;                // buffer for the intermediate passes (nullptr: out)
   const ntt_plan* const* plans; // num_limbs plans
   uint32_t num_limbs;

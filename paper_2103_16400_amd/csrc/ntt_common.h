@@ -11,12 +11,12 @@ namespace nttamd {
 
 constexpr int kMaxPlansPerLaunch = NTT_MAX_LIMBS;
 
-enum : u32 { kFlagLast = 1u, kFlagCanon = 2u, kFlagMul = 4u };
+enum : u32 { kFlagLast = 1u, kFlagCanon = 2u, kFlagMul = 4u, kFlagAcc = 8u };
 
 struct PassArgs {
   u64* out;
   const u64* in;
-  const u64* mul;                          // fused multiply operand (kFlagMul), same layout as out
+  const u64* mul;                          // kFlagMul: multiplier; kFlagAcc: accumulator (== out); same layout as out
   const u64* plan[kMaxPlansPerLaunch];     // device plan buffers; item y uses plan[y % num_limbs]
   u32 num_limbs;
   u32 logN;
@@ -71,11 +71,12 @@ __device__ __forceinline__ PlanView load_plan(const u64* plan, bool fwd, u64 N) 
 // Output step of the last pass: final correction, or the fused element-wise
 // product with the multiplier operand (forward transform of a product).
 // Output modes of the last pass, as template arguments of the kernels.
-enum OutMode : int { kOutLazy = 0, kOutCanon = 1, kOutMul = 2 };
+enum OutMode : int { kOutLazy = 0, kOutCanon = 1, kOutMul = 2, kOutAcc = 3 };
 
 template <bool FWD, int MODE>
 __device__ __forceinline__ u64 finish_mode(u64 v, u64 idx, const PassArgs& a, const PlanView& pv) {
   if (FWD && MODE == kOutMul) return barrett_mulmod<4>(v, a.mul[idx], pv.q, pv.q2, pv.bk, pv.qbits);
+  if (!FWD && MODE == kOutAcc) return csub(a.mul[idx] + csub(v, pv.q), pv.q);   // acc + InvNTT, acc < q
   if (MODE == kOutCanon) return FWD ? reduce4(v, pv.q, pv.q2) : csub(v, pv.q);
   return v;
 }
@@ -92,6 +93,7 @@ __device__ __forceinline__ u64 finish(u64 v, u64 idx, const PassArgs& a, const P
     if (a.flags & kFlagCanon) return reduce4(v, pv.q, pv.q2);
     return v;
   }
+  if (a.flags & kFlagAcc) return csub(a.mul[idx] + csub(v, pv.q), pv.q);
   return (a.flags & kFlagCanon) ? csub(v, pv.q) : v;
 }
 

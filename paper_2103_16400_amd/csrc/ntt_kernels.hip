@@ -257,6 +257,7 @@ static ntt_status launch_passes(const NttLaunch& l, bool fwd) {
     a.flags = kFlagLast;
     if (l.out_f == 1) a.flags |= kFlagCanon;
     if (fwd && l.mul_into) a.flags |= kFlagMul;
+    if (!fwd && l.mul_into) a.flags |= kFlagAcc;
     ntt_status st = launch_onchip(a, items, fwd, l.stream);
     if (st) return st;
     return hipGetLastError() == hipSuccess ? NTT_OK : NTT_EDEVICE;
@@ -276,6 +277,7 @@ static ntt_status launch_passes(const NttLaunch& l, bool fwd) {
       a.flags |= kFlagLast;
       if (l.out_f == 1) a.flags |= kFlagCanon;
       if (fwd && l.mul_into) a.flags |= kFlagMul;
+      if (!fwd && l.mul_into) a.flags |= kFlagAcc;
     }
     const int nt = 1 << (s.logt + s.logc + s.logh - s.logr);
     uint64_t tiles;

@@ -35,7 +35,7 @@ struct OnChip {
   static constexpr int NT = N >> LOGR;
   static constexpr int LDSW = N + (N >> LOGR);
   static constexpr int PERM_TOP = onchip_perm_top(FWD, LOGN);
-  static constexpr int TB = FWD ? 4 : 2;           // twiddle pairs per prefetch block
+  static constexpr int TB = 2;                      // twiddle pairs per prefetch block
   using G = Geo<FWD, LOGN, LOGR>;
   using W = typename std::conditional<SPLIT, u32, u64>::type;
 
@@ -104,12 +104,26 @@ struct OnChip {
     return pv.tw[((N + rho<r>(t, 0)) >> (bit + 1)) + (u32)u];
   }
 
+  // number of twiddle blocks of stage s in round r
+  template <int r>
+  static constexpr int nblocks(int s) {
+    return ((R >> ((FWD ? (G::first_bit(r) - s) : (G::first_bit(r) + s)) - G::lo(r) + 1)) + TB - 1) / TB;
+  }
+  // first step (global block counter) of stage s in round r
+  template <int r>
+  static constexpr int first_step(int s) {
+    int n = 0;
+    for (int i = 0; i < s; ++i) n += nblocks<r>(i);
+    return n;
+  }
+
   template <int r>
   __device__ static __forceinline__ void stages(u64 (&x)[R], u32 t, const PlanView& pv) {
     constexpr int lo = G::lo(r);
     constexpr int NS = G::nst(r);
-    ulonglong2 cur[TB], nxt[TB];
-    // blocks: stage s has n = R >> (p + 1) twiddles, grouped TB at a time
+    // two twiddle buffers used alternately by consecutive blocks (ping-pong on
+    // the compile-time block counter, so no register copies are needed)
+    ulonglong2 buf[2][TB];
     auto load_block = [&](ulonglong2 (&dst)[TB], int s, int blk) {
       const int bit = FWD ? (G::first_bit(r) - s) : (G::first_bit(r) + s);
       const int p = bit - lo;
@@ -120,7 +134,7 @@ struct OnChip {
       for (int i = 0; i < TB; ++i)
         if (blk * TB + i < n) dst[i] = twiddle<r>(pv, t, bit, blk * TB + i);
     };
-    load_block(cur, 0, 0);
+    load_block(buf[0], 0, 0);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int bit = FWD ? (G::first_bit(r) - s) : (G::first_bit(r) + s);
@@ -130,6 +144,9 @@ struct OnChip {
       const bool fused_last = !FWD && bit == LOGN - 1;
 #pragma unroll
       for (int blk = 0; blk < nb; ++blk) {
+        const int step = first_step<r>(s) + blk;
+        ulonglong2 (&cur)[TB] = buf[step & 1];
+        ulonglong2 (&nxt)[TB] = buf[(step + 1) & 1];
         if (blk + 1 < nb) load_block(nxt, s, blk + 1);
         else if (s + 1 < NS) load_block(nxt, s + 1, 0);
 #pragma unroll
@@ -146,8 +163,6 @@ struct OnChip {
           }
         }
         stage_fence();
-#pragma unroll
-        for (int i = 0; i < TB; ++i) cur[i] = nxt[i];
       }
     }
   }
@@ -237,6 +252,7 @@ static OnchipKernel pick_onchip(bool fwd, int logN, u32 flags) {
     if (flags & kFlagCanon) return pick_onchip_mode<true, kOutCanon>(logN);
     return pick_onchip_mode<true, kOutLazy>(logN);
   }
+  if (flags & kFlagAcc) return pick_onchip_mode<false, kOutAcc>(logN);
   if (flags & kFlagCanon) return pick_onchip_mode<false, kOutCanon>(logN);
   return pick_onchip_mode<false, kOutLazy>(logN);
 }

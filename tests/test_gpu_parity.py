@@ -293,3 +293,64 @@ def test_poly_mul_rns(nt, logN, L, B):
     da = to_dev(a)
     nt.poly_mul_rns(da, da, to_dev(b), N, moduli, B, ws)
     assert np.array_equal(from_dev(da), out)
+
+
+@pytest.mark.parametrize("logN,L,B", [(3, 2, 2), (11, 3, 2), (14, 8, 1), (15, 2, 1), (17, 1, 1)])
+def test_fused_forward_mul_and_inverse_acc(nt, logN, L, B):
+    N = 1 << logN
+    moduli = PRIMES["serving"]["moduli"][5:5 + L]
+    a = _rns_inputs(70, N, moduli, B, 4)               # operand with input factor 4
+    m = _rns_inputs(71, N, moduli, B, 4)               # lazy multiplier in [0, 4q)
+    acc0 = _rns_inputs(72, N, moduli, B, 1)
+    A2 = _rns_inputs(73, N, moduli, B, 2)              # inverse operand with input factor 2
+    ws = empty_dev(a.size)
+    dm = to_dev(m)
+    r = empty_dev(a.size)
+    nt.ntt_forward_mul_rns(r, to_dev(a), dm, N, moduli, B, 4, ws)
+    out = from_dev(r)
+    dacc = to_dev(acc0)
+    nt.ntt_inverse_acc_rns(dacc, to_dev(A2), N, moduli, B, 2, ws)
+    acc = from_dev(dacc)
+    idx = _sample_idx(N, 74, 12)
+    psis = {q: oracle.min_root(N, q) for q in moduli}
+    for p in range(B):
+        for l, q in enumerate(moduli):
+            s = slice((p * L + l) * N, (p * L + l + 1) * N)
+            if N <= 4096:
+                fa = oracle.ntt_forward(a[s], q, psis[q])
+                assert np.array_equal(out[s], oracle.eltwise_mult(fa, m[s], q))
+                ia = oracle.ntt_inverse(A2[s], q, psis[q])
+                assert np.array_equal(acc[s], oracle.eltwise_add(acc0[s], ia, q))
+            else:
+                fa = oracle.ntt_forward_at(a[s], idx, q, psis[q])
+                assert np.array_equal(out[s][idx], oracle.eltwise_mult(fa, m[s][idx], q))
+                ia = oracle.ntt_inverse_at(A2[s], idx, q, psis[q])
+                assert np.array_equal(acc[s][idx], oracle.eltwise_add(acc0[s][idx], ia, q))
+    # in place: result == multiplier
+    nt.ntt_forward_mul_rns(dm, to_dev(a), dm, N, moduli, B, 4, ws)
+    assert np.array_equal(from_dev(dm), out)
+
+
+@pytest.mark.parametrize("logN,L,B", [(5, 3, 2), (12, 4, 2), (14, 8, 2), (16, 2, 1)])
+def test_poly_mul_acc_rns(nt, logN, L, B):
+    N = 1 << logN
+    moduli = PRIMES["serving"]["moduli"][10:10 + L]
+    a = _rns_inputs(80, N, moduli, B)
+    b = _rns_inputs(81, N, moduli, B)
+    acc0 = _rns_inputs(82, N, moduli, B)
+    dacc = to_dev(acc0)
+    ws = empty_dev(2 * a.size)
+    nt.poly_mul_acc_rns(dacc, to_dev(a), to_dev(b), N, moduli, B, ws)
+    nt.poly_mul_acc_rns(dacc, to_dev(a), to_dev(b), N, moduli, B, ws)     # twice: acc + 2ab
+    acc = from_dev(dacc)
+    idx = _sample_idx(N, 83, 10)
+    for p in range(B):
+        for l, q in enumerate(moduli):
+            s = slice((p * L + l) * N, (p * L + l + 1) * N)
+            if N <= 1024:
+                ab = oracle.negacyclic_mul(a[s], b[s], q)
+                assert np.array_equal(acc[s], oracle.eltwise_add(oracle.eltwise_add(acc0[s], ab, q), ab, q))
+            else:
+                ab = oracle.negacyclic_mul_at(a[s], b[s], idx, q)
+                ref = oracle.eltwise_add(oracle.eltwise_add(acc0[s][idx], ab, q), ab, q)
+                assert np.array_equal(acc[s][idx], ref)
