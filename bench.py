@@ -67,6 +67,69 @@ def cpu_baseline(N, moduli, psis, budget_s=12.0):
                       "definition, %d threads, %.1f s" % (done, N, min(done, len(moduli)), threads, el)}
 
 
+def time_large_ring(nt, torch, primes, reps=20):
+    """Forward and inverse NTT of 32-limb polynomials at N = 2^16 (60-bit primes), one
+    launch sequence per batch of B polynomials, rotating over 16 distinct polynomials
+    (256 MiB) so coefficients come from HBM rather than the 256 MB MALL."""
+    p3 = primes["large_65536"]
+    N, moduli = p3["N"], p3["moduli"]
+    L = len(moduli)
+    pool = 16
+    dev = torch.device("cuda:0")
+    data = torch.from_numpy(gen_operand(3, N, moduli, pool).view(np.int64)).to(dev)
+    ws = torch.empty(8 * L * N, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for B in (1, 2, 8):
+        views = [data[i * L * N:(i + B) * L * N] for i in range(0, pool - B + 1, B)]
+        res = {}
+        for name, fn in (("fwd", lambda v: nt.ntt_forward_rns(v, v, N, moduli, B, 1, 4, stream=stream)),
+                         ("fwd_canon", lambda v: nt.ntt_forward_rns(v, v, N, moduli, B, 1, 1, stream=stream)),
+                         ("inv", lambda v: nt.ntt_inverse_rns(v, v, N, moduli, B, 1, 2, stream=stream))):
+            for v in views[:2]:
+                fn(v)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for r in range(reps):
+                fn(views[r % len(views)])
+            e1.record(stream)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / reps
+            alg = B * 16 * N * L + 16 * N * L          # coefficients read+written + one table per prime
+            res[name + "_us"] = round(us, 2)
+            res[name + "_hbm_frac"] = round(alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+        res["limb_ntts_per_s_fwd"] = round(B * L / (res["fwd_us"] * 1e-6), 1)
+        out["B%d" % B] = res
+    out["alg_bytes_B1"] = 16 * N * L + 16 * N * L
+    return out
+
+
+def time_single_1024(nt, torch, primes, reps=200):
+    """Per-call latency of one forward and one inverse NTT at N = 1024 (single limb)."""
+    p1 = primes["single_1024"]
+    N, q = p1["N"], p1["moduli"][0]
+    from synthetic import uniform_mod, unit_seed
+    dev = torch.device("cuda:0")
+    a = torch.from_numpy(uniform_mod(unit_seed(1, 1), N, q).view(np.int64)).to(dev)
+    o = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, fn in (("fwd", lambda: nt.ntt_forward(o, a, N, q, 1, 1, stream=stream)),
+                     ("inv", lambda: nt.ntt_inverse(o, a, N, q, 1, 1, stream=stream))):
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[name + "_us_per_call"] = round(e0.elapsed_time(e1) * 1e3 / reps, 3)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +138,7 @@ def main():
     ap.add_argument("--polys", type=int, default=512, help="RNS polynomials per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; the path shards over GPUs by limbs "
@@ -153,6 +217,11 @@ def main():
         "fwd_ntt_rate": round(limbs / (fwd_ms * 1e-3), 1),
         "products_per_s": round(limbs / (wall / args.steps), 1),
     }
+    if not args.no_extra:
+        del a, b, c, ws, acc
+        torch.cuda.empty_cache()
+        out["large_ring_n65536_l32"] = time_large_ring(nt, torch, load_primes())
+        out["single_n1024"] = time_single_1024(nt, torch, load_primes())
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, moduli, psis, args.cpu_seconds)
     print(json.dumps(out), flush=True)
