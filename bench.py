@@ -83,6 +83,7 @@ def time_large_ring(nt, torch, primes, reps=20):
     for B in (1, 2, 8):
         views = [data[i * L * N:(i + B) * L * N] for i in range(0, pool - B + 1, B)]
         res = {}
+        res["autotune_variant_fwd_inv"] = list(nt.autotune(N, moduli, B, stream=stream))
         for name, fn in (("fwd", lambda v: nt.ntt_forward_rns(v, v, N, moduli, B, 1, 4, stream=stream)),
                          ("fwd_canon", lambda v: nt.ntt_forward_rns(v, v, N, moduli, B, 1, 1, stream=stream)),
                          ("inv", lambda v: nt.ntt_inverse_rns(v, v, N, moduli, B, 1, 2, stream=stream))):

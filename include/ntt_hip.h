@@ -208,6 +208,22 @@ ntt_status poly_mul_acc_rns(uint64_t* acc, const uint64_t* a, const uint64_t* b,
                             const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
                             uint64_t* workspace, ntt_stream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Autotuning (the paper's Section 4 remark that the best implementation could
+ * be chosen by "a small number of trials" at initialisation).  For two-pass
+ * sizes (N > 2^14) the library has several kernel variants per pass; this call
+ * times each on a scratch buffer of num_limbs * num_polys * N words (allocated
+ * and freed here, so it is not a hot-path call), synchronises `stream`, and
+ * uses the fastest for later calls of the same direction, N and batch-size
+ * class (up to 64 limbs, or more).  choice_fwd / choice_inv (may be NULL)
+ * receive the chosen variant indices.  N <= 2^14 has a single variant.
+ * ntt_set_variant pins a variant explicitly (forward != 0 for the forward
+ * transform); NTT_EINVAL_COUNT for an unknown variant.
+ */
+ntt_status ntt_autotune(uint64_t N, const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
+                        ntt_stream_t stream, int* choice_fwd, int* choice_inv);
+ntt_status ntt_set_variant(uint64_t N, uint64_t num_items, int forward, int variant);
+
 #ifdef __cplusplus
 }
 #endif

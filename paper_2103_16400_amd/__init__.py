@@ -45,6 +45,8 @@ _SIGS = {
     "ntt_forward_mul_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _U64, _P, _P]),
     "ntt_inverse_acc_rns": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _P, _P]),
     "poly_mul_acc_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P, _P]),
+    "ntt_autotune": (_ST, [_U64, _P, _U64, _U64, _P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "ntt_set_variant": (_ST, [_U64, _U64, ctypes.c_int, ctypes.c_int]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -210,6 +212,18 @@ def poly_mul_acc_rns(acc, a, b, N, moduli, num_polys, workspace, stream=None):
     m, L = _moduli(moduli)
     _check(_lib.poly_mul_acc_rns(_ptr(acc), _ptr(a), _ptr(b), N, m, L, num_polys, _ptr(workspace),
                                  _stream(stream)), "poly_mul_acc_rns")
+
+
+def autotune(N, moduli, num_polys, stream=None):
+    """Times the kernel variants for this shape and keeps the fastest; returns (fwd, inv) choices."""
+    m, L = _moduli(moduli)
+    f, i = ctypes.c_int(0), ctypes.c_int(0)
+    _check(_lib.ntt_autotune(N, m, L, num_polys, _stream(stream), ctypes.byref(f), ctypes.byref(i)), "ntt_autotune")
+    return f.value, i.value
+
+
+def set_variant(N, num_items, forward, variant):
+    _check(_lib.ntt_set_variant(N, num_items, 1 if forward else 0, variant), "ntt_set_variant")
 
 
 def shutdown():

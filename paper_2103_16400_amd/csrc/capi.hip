@@ -308,4 +308,61 @@ ntt_status poly_mul_acc_rns(uint64_t* acc, const uint64_t* a, const uint64_t* b,
   return ntt_rns(false, acc, prod, acc, one_pass ? nullptr : prod, N, moduli, num_limbs, num_polys, 1, 1, stream);
 }
 
+ntt_status ntt_autotune(uint64_t N, const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
+                        ntt_stream_t stream, int* choice_fwd, int* choice_inv) {
+  if (!moduli) return NTT_EINVAL_POINTER;
+  if (num_limbs == 0 || num_limbs > NTT_MAX_LIMBS || num_polys == 0) return NTT_EINVAL_COUNT;
+  ntt_status st = validate_degree(N);
+  if (st) return st;
+  if (num_polys > (1ull << 36) / (num_limbs * N)) return NTT_EINVAL_COUNT;
+  std::vector<const ntt_plan*> plans;
+  st = rns_plans(N, moduli, num_limbs, plans);
+  if (st) return st;
+  const int logN = plans[0]->logN;
+  const uint64_t items = num_limbs * num_polys;
+  int best[2] = {0, 0};
+  if (pass_count(logN) > 1) {
+    // scratch on the device for timing only (not a hot-path call)
+    uint64_t* buf = nullptr;
+    const size_t bytes = (size_t)(items * N * sizeof(uint64_t));
+    if (hipMalloc((void**)&buf, bytes) != hipSuccess) return NTT_ENOMEM;
+    if (hipMemsetAsync(buf, 0, bytes, (hipStream_t)stream) != hipSuccess) { (void)hipFree(buf); return NTT_EDEVICE; }
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    for (int dir = 0; dir < 2; ++dir) {
+      float best_ms = 1e30f;
+      for (int v = 0; v < hi_variant_count(); ++v) {
+        NttLaunch l{buf, buf, nullptr, nullptr, plans.data(), (uint32_t)num_limbs, num_polys, 1, dir ? 4u : 2u,
+                    (hipStream_t)stream};
+        for (int w = 0; w < 2; ++w) launch_variant(l, dir == 1, v);
+        (void)hipEventRecord(e0, (hipStream_t)stream);
+        for (int r = 0; r < 5; ++r) launch_variant(l, dir == 1, v);
+        (void)hipEventRecord(e1, (hipStream_t)stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) { best_ms = ms; best[dir] = v; }
+      }
+      set_hi_variant(dir == 1, logN, items, best[dir]);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(buf);
+  }
+  if (choice_fwd) *choice_fwd = best[1];
+  if (choice_inv) *choice_inv = best[0];
+  return NTT_OK;
+}
+
+ntt_status ntt_set_variant(uint64_t N, uint64_t num_items, int forward, int variant) {
+  ntt_status st = validate_degree(N);
+  if (st) return st;
+  int logN = 0;
+  while ((1ull << logN) < N) ++logN;
+  if (variant < 0 || variant >= hi_variant_count()) return NTT_EINVAL_COUNT;
+  if (pass_count(logN) > 1) set_hi_variant(forward != 0, logN, num_items, variant);
+  return NTT_OK;
+}
+
 }  // extern "C"

@@ -13,9 +13,8 @@ namespace nttamd {
 //   [0, 16)                 header, see PlanHeader
 //   [16, 16 + 2N)           forward pairs (W, W') at index k: W = psi^brv(k)
 //   [16 + 2N, 16 + 4N)      inverse pairs at index k: W = psi^-brv(k)
-//   [16 + 4N, 16 + 8N)      (N <= 2^14 only) the same two tables with the
-//                           sub-tables of the finest stages transposed for the
-//                           single-pass kernel, see onchip_perm_top()
+//   [16 + 4N, 16 + 8N)      the same two tables with the sub-tables of the
+//                           finest stages transposed, see table_perm()
 struct PlanHeader {
   uint64_t q, q2, nq, N;      // q, 2q, 2^64 - q, degree
   uint64_t ninv, ninv_p;      // N^{-1} mod q and floor(N^{-1} 2^64 / q)
@@ -34,15 +33,40 @@ __host__ __device__ constexpr int onchip_logr(int logN) { return logN <= 4 ? log
 // entries (N >> (b+1)) + t*S + u, u < S = 2^(logr-1-b).  Those sub-tables are
 // stored transposed, entry (N >> (b+1)) + u*(N >> logr) + t, so that the 64
 // lanes of a wave read 1 KiB contiguous per instruction.  Returns top (-1: none).
-__host__ __device__ constexpr int onchip_perm_top(bool fwd, int logN) {
-  const int logr = onchip_logr(logN);
+// Same rule for a transform (or pass) over `logt` index bits with 2^logr
+// coefficients per thread, whose forward runs from the top bit down.
+__host__ __device__ constexpr int perm_top_for(bool fwd, int logt, int logr) {
   int top = logr - 2;
+  if (top > logt - 1) top = logt - 1;
   if (fwd) {
-    const int nr = (logN + logr - 1) / logr;
-    const int first = logN - 1 - (nr - 1) * logr;   // highest bit handled by the last round
+    const int nr = (logt + logr - 1) / logr;
+    const int first = logt - 1 - (nr - 1) * logr;   // highest bit handled by the last round
     if (first < top) top = first;
   }
   return top;
+}
+__host__ __device__ constexpr int onchip_perm_top(bool fwd, int logN) {
+  return perm_top_for(fwd, logN, onchip_logr(logN));
+}
+
+// Two-pass schedule for 2^15 <= N <= 2^17 (the Cooley-Tukey split N = N1 N2):
+// the "high" pass covers the top index bits as strided sub-transforms over
+// tiles of adjacent columns, the "low" pass the bottom mp_logt_lo bits as
+// contiguous blocks with 2^kMpLogrLo coefficients per thread.
+constexpr int kMpLogrLo = 4;
+__host__ __device__ constexpr int mp_logt_lo(int logN) { return logN == 15 ? 7 : 8; }
+__host__ __device__ constexpr int mp_logt_hi(int logN) { return logN - mp_logt_lo(logN); }
+__host__ __device__ constexpr int mp_perm_top(bool fwd, int logN) {
+  return perm_top_for(fwd, mp_logt_lo(logN), kMpLogrLo);
+}
+// Which finest-stage sub-tables a plan stores transposed, and with what thread
+// stride: bits 0..top, entry (N >> (b+1)) + t*S + u  ->  (N >> (b+1)) + u*(N >> logr) + t.
+struct TablePerm {
+  int logr, top_fwd, top_inv;
+};
+__host__ __device__ constexpr TablePerm table_perm(int logN) {
+  return logN <= kMaxOnchipLog ? TablePerm{onchip_logr(logN), onchip_perm_top(true, logN), onchip_perm_top(false, logN)}
+                               : TablePerm{kMpLogrLo, mp_perm_top(true, logN), mp_perm_top(false, logN)};
 }
 
 }  // namespace nttamd
@@ -83,6 +107,11 @@ struct NttLaunch {
 };
 ntt_status launch_forward(const NttLaunch& l);
 int pass_count(int logN);
+// autotuner hooks (ntt_kernels.hip): variants of the high pass of two-pass transforms
+ntt_status launch_variant(const NttLaunch& l, bool fwd, int variant);
+void set_hi_variant(bool fwd, int logN, uint64_t items, int variant);
+int get_hi_variant(bool fwd, int logN, uint64_t items);
+int hi_variant_count();
 ntt_status launch_inverse(const NttLaunch& l);
 
 struct EltLaunch {

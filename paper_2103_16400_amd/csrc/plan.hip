@@ -140,8 +140,7 @@ ntt_status build_plan(ntt_plan** out, uint64_t N, uint64_t q, uint64_t psi) {
   const int logN = log2_exact(N);
   const uint64_t psi_inv = pow_mod(psi, 2 * N - 1, q);
 
-  const bool onchip = logN <= kMaxOnchipLog;
-  std::vector<uint64_t> host(kPlanHeaderWords + (onchip ? 8 : 4) * N, 0);
+  std::vector<uint64_t> host(kPlanHeaderWords + 8 * N, 0);
   // powers psi^i and psi^-i, i < N, then the bit-reversed pair tables
   std::vector<uint64_t> pw(N), pwi(N);
   pw[0] = pwi[0] = 1;
@@ -158,15 +157,16 @@ ntt_status build_plan(ntt_plan** out, uint64_t N, uint64_t q, uint64_t psi) {
     inv[2 * k] = pwi[r];
     inv[2 * k + 1] = shoup(pwi[r], q);
   }
-  if (onchip) {
-    // transposed copies for the single-pass kernel (see onchip_perm_top)
-    const int logr = onchip_logr(logN);
+  {
+    // transposed copies of the finest stages' sub-tables (see table_perm)
+    const TablePerm tp = table_perm(logN);
+    const int logr = tp.logr;
     const uint64_t R = 1ull << logr, NT = N >> logr;
     for (int dir = 0; dir < 2; ++dir) {
       const uint64_t* src = fwd + dir * 2 * N;
       uint64_t* dst = fwd + 4 * N + dir * 2 * N;
       std::memcpy(dst, src, 2 * N * sizeof(uint64_t));
-      const int top = onchip_perm_top(dir == 0, logN);
+      const int top = dir == 0 ? tp.top_fwd : tp.top_inv;
       for (int b = 0; b <= top; ++b) {
         const uint64_t base = N >> (b + 1), S = R >> (b + 1);
         for (uint64_t t = 0; t < NT; ++t)
