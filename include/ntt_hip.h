@@ -209,6 +209,56 @@ ntt_status poly_mul_acc_rns(uint64_t* acc, const uint64_t* a, const uint64_t* b,
                             uint64_t* workspace, ntt_stream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Batches of limb tasks with uneven ring degrees in one persistent launch.
+ * RNS polynomials of different sizes and limb counts (Section 5) are lists of
+ * independent limb transforms; a batch runs any mix of them in one kernel
+ * launch (workgroups claim tasks from a device-side counter, largest first).
+ *
+ * ntt_batch_item: one limb task, N in [2^10, 2^17], q its modulus (plans come
+ *   from the library cache, smallest psi), device pointers to N words each:
+ *     op NTT_BATCH_FWD_LAZY   out = NTT(in) in [0, 4q), in < q   (forward 1 -> 4)
+ *        NTT_BATCH_FWD        out = NTT(in) canonical           (forward 1 -> 1)
+ *        NTT_BATCH_INV_LAZY   out = InvNTT(in) in [0, 2q)       (inverse 1 -> 2)
+ *        NTT_BATCH_INV        out = InvNTT(in) canonical        (inverse 1 -> 1)
+ *        NTT_BATCH_PRODUCT    out = in * in2 mod (X^N + 1, q), canonical (the
+ *                             Section 4 product listing); tmp: N-word
+ *                             workspace, required for N > 2^14, else ignored
+ *   out may equal in; for products out must not overlap in2 or tmp.
+ * ntt_batch_create: a reusable batch context for up to `capacity` tasks (owns
+ *   pinned and device descriptor buffers; not thread-safe: one context per
+ *   host thread or external locking).
+ * ntt_batch_run: copies the descriptors and launches, asynchronously on
+ *   `stream` (waits first for the context's previous run to release its
+ *   staging buffer).  Errors: NTT_EINVAL_* for a bad task (nothing launched).
+ * ntt_batch_run_graph: same work through a hipGraph captured on first use:
+ *   [descriptor copy, counter reset, persistent kernel]; the graph reads the
+ *   task list and count from device memory, so it is replayed unchanged for
+ *   every later batch of up to `capacity` tasks.
+ * ntt_batch_set_grid: number of persistent workgroups (0 = two per CU).
+ */
+typedef struct ntt_batch ntt_batch;
+#define NTT_BATCH_FWD_LAZY 0u
+#define NTT_BATCH_FWD 1u
+#define NTT_BATCH_INV_LAZY 2u
+#define NTT_BATCH_INV 3u
+#define NTT_BATCH_PRODUCT 4u
+typedef struct {
+  uint64_t* out;
+  const uint64_t* in;
+  const uint64_t* in2;
+  uint64_t* tmp;
+  uint64_t N;
+  uint64_t q;
+  uint32_t op;
+  uint32_t reserved;
+} ntt_batch_item;
+ntt_status ntt_batch_create(ntt_batch** batch, size_t capacity);
+ntt_status ntt_batch_destroy(ntt_batch* batch);
+ntt_status ntt_batch_set_grid(ntt_batch* batch, int workgroups);
+ntt_status ntt_batch_run(ntt_batch* batch, const ntt_batch_item* items, size_t count, ntt_stream_t stream);
+ntt_status ntt_batch_run_graph(ntt_batch* batch, const ntt_batch_item* items, size_t count, ntt_stream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Autotuning (the paper's Section 4 remark that the best implementation could
  * be chosen by "a small number of trials" at initialisation).  For two-pass
  * sizes (N > 2^14) the library has several kernel variants per pass; this call

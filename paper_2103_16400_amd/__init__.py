@@ -45,6 +45,11 @@ _SIGS = {
     "ntt_forward_mul_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _U64, _P, _P]),
     "ntt_inverse_acc_rns": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _P, _P]),
     "poly_mul_acc_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P, _P]),
+    "ntt_batch_create": (_ST, [ctypes.POINTER(_P), ctypes.c_size_t]),
+    "ntt_batch_destroy": (_ST, [_P]),
+    "ntt_batch_set_grid": (_ST, [_P, ctypes.c_int]),
+    "ntt_batch_run": (_ST, [_P, _P, ctypes.c_size_t, _P]),
+    "ntt_batch_run_graph": (_ST, [_P, _P, ctypes.c_size_t, _P]),
     "ntt_autotune": (_ST, [_U64, _P, _U64, _U64, _P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "ntt_set_variant": (_ST, [_U64, _U64, ctypes.c_int, ctypes.c_int]),
 }
@@ -224,6 +229,60 @@ def autotune(N, moduli, num_polys, stream=None):
 
 def set_variant(N, num_items, forward, variant):
     _check(_lib.ntt_set_variant(N, num_items, 1 if forward else 0, variant), "ntt_set_variant")
+
+
+class BatchItem(ctypes.Structure):
+    """ntt_batch_item of include/ntt_hip.h."""
+    _fields_ = [("out", _P), ("in_", _P), ("in2", _P), ("tmp", _P), ("N", _U64), ("q", _U64),
+                ("op", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+BATCH_FWD_LAZY, BATCH_FWD, BATCH_INV_LAZY, BATCH_INV, BATCH_PRODUCT = 0, 1, 2, 3, 4
+
+
+class Batch:
+    """A reusable batch context: runs lists of limb tasks of mixed N in one persistent launch."""
+
+    def __init__(self, capacity: int):
+        h = _P()
+        _check(_lib.ntt_batch_create(ctypes.byref(h), capacity), "ntt_batch_create")
+        self._h = h
+        self.capacity = capacity
+
+    def close(self):
+        if self._h:
+            _lib.ntt_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_grid(self, workgroups: int):
+        _check(_lib.ntt_batch_set_grid(self._h, workgroups), "ntt_batch_set_grid")
+
+    @staticmethod
+    def make_items(tasks):
+        """tasks: iterable of (op, out, in, in2, tmp, N, q) with torch tensors (or None)."""
+        tasks = list(tasks)
+        arr = (BatchItem * max(1, len(tasks)))()
+        for k, (op, out, inp, in2, tmp, N, q) in enumerate(tasks):
+            arr[k].out = _ptr(out)
+            arr[k].in_ = _ptr(inp)
+            arr[k].in2 = _ptr(in2)
+            arr[k].tmp = _ptr(tmp)
+            arr[k].N = N
+            arr[k].q = q
+            arr[k].op = op
+        return arr, len(tasks)
+
+    def run(self, items, count=None, stream=None, graph=False):
+        if not isinstance(items, ctypes.Array):
+            items, count = self.make_items(items)
+        fn = _lib.ntt_batch_run_graph if graph else _lib.ntt_batch_run
+        _check(fn(self._h, items, count, _stream(stream)), "ntt_batch_run_graph" if graph else "ntt_batch_run")
 
 
 def shutdown():

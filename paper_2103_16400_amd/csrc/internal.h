@@ -92,6 +92,17 @@ ntt_status cached_plan(uint64_t N, uint64_t q, const ntt_plan** out);
 void clear_plan_cache();
 uint64_t barrett_factor(uint64_t q, uint32_t* qbits);
 
+// One limb task of the persistent batch kernel (ntt_batch.hip).
+struct BatchTask {
+  uint64_t* out;
+  const uint64_t* in;
+  const uint64_t* in2;      // second product factor
+  uint64_t* tmp;            // product workspace (N > 2^14)
+  const uint64_t* plan;
+  uint32_t logN, op;
+};
+enum : uint32_t { kBatchFwdLazy = 0, kBatchFwdCanon = 1, kBatchInvLazy = 2, kBatchInvCanon = 3, kBatchProduct = 4 };
+
 // Kernel launchers (ntt_kernels.hip / eltwise.hip).
 struct NttLaunch {
   uint64_t* out;

@@ -1,0 +1,338 @@
+// Persistent batch kernel: one launch runs a list of limb tasks of mixed ring
+// degree (2^10 .. 2^17), moduli and operation.
+//
+// RNS polynomials of different sizes and limb counts (Section 5) decompose
+// into independent limb tasks.  Each workgroup of the persistent grid claims
+// the next task from a device-side counter (tasks are ordered largest first)
+// and runs it to completion by itself, so tasks never wait on each other:
+//   * N <= 2^14: the single-pass transform held on chip (ntt_onchip.h), with
+//     2^(logN-9) coefficients per thread so every size uses 512 threads;
+//   * N >= 2^15: both passes of the two-pass transform (ntt_tile.h), one
+//     4096-coefficient tile at a time; the intermediate stays in the limb's
+//     output buffer and the workgroup barrier orders the passes.
+// Operations: forward (lazy [0, 4q) or canonical), inverse (lazy [0, 2q) or
+// canonical) and the negacyclic product out = a * b of the Section 4 listing
+// (forward(a), forward(b) fused with the multiply, inverse).  The task list
+// and its length live in device memory, so a captured graph of
+// [descriptor copy, counter reset, kernel] can be replayed for any batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+#include "modarith.h"
+#include "ntt_common.h"
+#include "ntt_onchip.h"
+#include "ntt_tile.h"
+
+struct ntt_batch {
+  int device;
+  size_t capacity;                 // tasks
+  nttamd::BatchTask* host;         // pinned staging: tasks then the count
+  nttamd::BatchTask* dev;          // device copy
+  uint32_t* dev_count;             // task count (device)
+  uint32_t* dev_counter;           // claim counter (device)
+  hipEvent_t done;                 // completion of the last run (staging reuse)
+  bool pending;
+  int grid;                        // persistent workgroups (0: automatic)
+  hipGraph_t graph;
+  hipGraphExec_t graph_exec;
+  hipStream_t graph_stream;
+};
+
+namespace nttamd {
+
+constexpr int kBatchThreads = 512;
+constexpr int kBatchLdsWords32 = (1 << 14) + (1 << 14) / 32;   // 2^14 split exchange, 66 KiB
+
+// ---- one task -----------------------------------------------------------------
+
+template <bool FWD, int LOGN, int MODE>
+__device__ __attribute__((noinline)) void task_onchip(const u64* plan, const u64* in, u64* out, const u64* mul, u32* lds,
+                                            bool nt) {
+  const PlanView pv = load_plan(plan, FWD, 1ull << LOGN);
+  onchip_body<FWD, LOGN, LOGN - 9, true, MODE>(pv, in, out, mul, lds, nt);
+}
+
+// Both passes of a two-pass transform by one workgroup (512 threads, tiles of
+// 4096 coefficients, 8 per thread).
+// `mid` receives the first pass (may equal out unless out holds the multiplier).
+template <bool FWD, int LOGN, int MODE>
+__device__ __attribute__((noinline)) void task_twopass(const u64* plan, const u64* in, u64* mid, u64* out, const u64* mul,
+                                             u64* lds, bool nt) {
+  constexpr int LT_LO = mp_logt_lo(LOGN);
+  constexpr int LT_HI = LOGN - LT_LO;
+  constexpr int LC_HI = 12 - LT_HI;           // columns per high-pass tile
+  constexpr int LH_LO = 12 - LT_LO;           // blocks per low-pass tile
+  constexpr int TILES = 1 << (LOGN - 12);
+  const PlanView pv = load_plan(plan, FWD, 1ull << LOGN);
+#pragma unroll 1
+  for (int step = 0; step < 2; ++step) {
+    const bool hi = FWD ? step == 0 : step == 1;
+    const bool last = step == 1;
+    const u64* src = step == 0 ? in : mid;
+    u64* dst = step == 0 ? mid : out;
+#pragma unroll 1
+    for (u32 tile = 0; tile < (u32)TILES; ++tile) {
+      if (hi) {
+        if (last) tile_body<FWD, LT_HI, 3, LC_HI, 0, MODE, true, -1>(pv, LOGN, LT_LO, tile, src, dst, mul, lds, false);
+        else tile_body<FWD, LT_HI, 3, LC_HI, 0, kOutLazy, false, -1>(pv, LOGN, LT_LO, tile, src, dst, mul, lds, nt);
+      } else {
+        if (last) tile_body<FWD, LT_LO, 3, 0, LH_LO, MODE, true, -1>(pv, LOGN, 0, tile, src, dst, mul, lds, false);
+        else tile_body<FWD, LT_LO, 3, 0, LH_LO, kOutLazy, false, -1>(pv, LOGN, 0, tile, src, dst, mul, lds, nt);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <bool FWD, int MODE>
+__device__ __forceinline__ void run_transform(u32 logN, const u64* plan, const u64* in, u64* mid, u64* out,
+                                              const u64* mul, void* lds, bool nt) {
+  u32* l32 = reinterpret_cast<u32*>(lds);
+  u64* l64 = reinterpret_cast<u64*>(lds);
+  switch (logN) {
+    case 10: task_onchip<FWD, 10, MODE>(plan, in, out, mul, l32, nt); break;
+    case 11: task_onchip<FWD, 11, MODE>(plan, in, out, mul, l32, nt); break;
+    case 12: task_onchip<FWD, 12, MODE>(plan, in, out, mul, l32, nt); break;
+    case 13: task_onchip<FWD, 13, MODE>(plan, in, out, mul, l32, nt); break;
+    case 14: task_onchip<FWD, 14, MODE>(plan, in, out, mul, l32, nt); break;
+    case 15: task_twopass<FWD, 15, MODE>(plan, in, mid, out, mul, l64, nt); break;
+    case 16: task_twopass<FWD, 16, MODE>(plan, in, mid, out, mul, l64, nt); break;
+    case 17: task_twopass<FWD, 17, MODE>(plan, in, mid, out, mul, l64, nt); break;
+    default: break;
+  }
+}
+
+__global__ void batch_reset_kernel(u32* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+__global__ void __launch_bounds__(kBatchThreads, 4)
+    ntt_batch_kernel(const BatchTask* __restrict__ tasks, const u32* __restrict__ count, u32* counter) {
+  __shared__ u32 lds[kBatchLdsWords32];
+  __shared__ u32 claimed;
+  const u32 n = *count;
+#pragma unroll 1
+  for (;;) {
+    if (threadIdx.x == 0) claimed = atomicAdd(counter, 1u);
+    __syncthreads();
+    const u32 i = claimed;
+    __syncthreads();
+    if (i >= n) break;                          // every wave of every workgroup reaches this exit
+    const BatchTask tk = tasks[i];
+    switch (tk.op) {
+      case kBatchFwdLazy: run_transform<true, kOutLazy>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true); break;
+      case kBatchFwdCanon: run_transform<true, kOutCanon>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true); break;
+      case kBatchInvLazy: run_transform<false, kOutLazy>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true); break;
+      case kBatchInvCanon: run_transform<false, kOutCanon>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true); break;
+      case kBatchProduct:
+        // out <- NTT(a) lazy; out <- NTT(b) (.) out (first pass of NTT(b) in tmp); out <- InvNTT(out)
+        run_transform<true, kOutLazy>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true);
+        __syncthreads();
+        run_transform<true, kOutMul>(tk.logN, tk.plan, tk.in2, tk.tmp, tk.out, tk.out, lds, true);
+        __syncthreads();
+        run_transform<false, kOutCanon>(tk.logN, tk.plan, tk.out, tk.out, tk.out, nullptr, lds, false);
+        break;
+      default: break;
+    }
+    __syncthreads();
+  }
+}
+
+// ---- host side ----------------------------------------------------------------
+
+static uint64_t task_cost(uint32_t logN, uint32_t op) {
+  const uint64_t n = 1ull << logN;
+  return n * logN * (op == kBatchProduct ? 3 : 1);
+}
+
+ntt_status batch_prepare(ntt_batch* b, const ntt_batch_item* items, size_t count, size_t* out_count) {
+  if (b->pending) {
+    if (hipEventSynchronize(b->done) != hipSuccess) return NTT_EDEVICE;   // staging still in use
+    b->pending = false;
+  }
+  std::vector<std::pair<uint64_t, size_t>> order(count);
+  for (size_t i = 0; i < count; ++i) {
+    const ntt_batch_item& it = items[i];
+    if (!it.out || !it.in) return NTT_EINVAL_POINTER;
+    ntt_status st = validate_degree(it.N);
+    if (st) return st;
+    if (it.N < 1024) return NTT_EINVAL_DEGREE;
+    int logN = 0;
+    while ((1ull << logN) < it.N) ++logN;
+    if (it.op > kBatchProduct) return NTT_EINVAL_FACTOR;
+    if (it.op == kBatchProduct && !it.in2) return NTT_EINVAL_POINTER;
+    if (it.op == kBatchProduct && logN > kMaxOnchipLog && !it.tmp) return NTT_EINVAL_POINTER;
+    const size_t bytes = (size_t)it.N * sizeof(uint64_t);
+    const uintptr_t o0 = (uintptr_t)it.out, i0 = (uintptr_t)it.in;
+    if (it.out != it.in && o0 < i0 + bytes && i0 < o0 + bytes) return NTT_EALIAS;
+    if (it.op == kBatchProduct) {
+      const uintptr_t b0 = (uintptr_t)it.in2;
+      if (o0 < b0 + bytes && b0 < o0 + bytes) return NTT_EALIAS;
+      if (logN > kMaxOnchipLog) {
+        const uintptr_t w0 = (uintptr_t)it.tmp;
+        if ((w0 < o0 + bytes && o0 < w0 + bytes) || (w0 < b0 + bytes && b0 < w0 + bytes) ||
+            (w0 < i0 + bytes && i0 < w0 + bytes))
+          return NTT_EALIAS;
+      }
+    }
+    order[i] = {task_cost((uint32_t)logN, it.op), i};
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [](const std::pair<uint64_t, size_t>& a, const std::pair<uint64_t, size_t>& c) {
+                     return a.first > c.first;
+                   });
+  for (size_t k = 0; k < count; ++k) {
+    const ntt_batch_item& it = items[order[k].second];
+    const ntt_plan* p = nullptr;
+    ntt_status st = cached_plan(it.N, it.q, &p);
+    if (st) return st;
+    BatchTask& t = b->host[k];
+    t.out = it.out;
+    t.in = it.in;
+    t.in2 = it.in2;
+    t.tmp = it.tmp;
+    t.plan = p->dev;
+    t.logN = (uint32_t)p->logN;
+    t.op = it.op;
+  }
+  *reinterpret_cast<uint32_t*>(b->host + b->capacity) = (uint32_t)count;
+  *out_count = count;
+  return NTT_OK;
+}
+
+int batch_grid(const ntt_batch* b, size_t count) {
+  int g = b->grid;
+  if (g <= 0) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    g = 2 * cus;                                // two 512-thread workgroups per CU (66 KiB LDS each)
+  }
+  if ((size_t)g > count) g = (int)count;
+  return g < 1 ? 1 : g;
+}
+
+// Enqueues [descriptor copy, counter reset, persistent kernel] on `stream`.
+ntt_status batch_enqueue(ntt_batch* b, int grid, hipStream_t stream) {
+  const size_t bytes = b->capacity * sizeof(BatchTask) + sizeof(uint32_t);
+  if (hipMemcpyAsync(b->dev, b->host, bytes, hipMemcpyHostToDevice, stream) != hipSuccess) return NTT_EDEVICE;
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, stream, b->dev_counter);
+  hipLaunchKernelGGL(ntt_batch_kernel, dim3(grid), dim3(kBatchThreads), 0, stream, b->dev, b->dev_count,
+                     b->dev_counter);
+  return hipGetLastError() == hipSuccess ? NTT_OK : NTT_EDEVICE;
+}
+
+}  // namespace nttamd
+
+using namespace nttamd;
+
+extern "C" {
+
+ntt_status ntt_batch_create(ntt_batch** out, size_t capacity) {
+  if (!out) return NTT_EINVAL_POINTER;
+  *out = nullptr;
+  if (capacity == 0 || capacity > (1u << 24)) return NTT_EINVAL_COUNT;
+  ntt_batch* b = new (std::nothrow) ntt_batch();
+  if (!b) return NTT_ENOMEM;
+  b->capacity = capacity;
+  const size_t bytes = capacity * sizeof(BatchTask) + sizeof(uint32_t);
+  if (hipGetDevice(&b->device) != hipSuccess) { delete b; return NTT_EDEVICE; }
+  if (hipHostMalloc((void**)&b->host, bytes, hipHostMallocDefault) != hipSuccess) { delete b; return NTT_ENOMEM; }
+  if (hipMalloc((void**)&b->dev, bytes + 256) != hipSuccess) {
+    (void)hipHostFree(b->host);
+    delete b;
+    return NTT_ENOMEM;
+  }
+  b->dev_count = reinterpret_cast<uint32_t*>(b->dev + capacity);
+  b->dev_counter = b->dev_count + 32;                     // separate 128-byte line
+  if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+    (void)hipFree(b->dev);
+    (void)hipHostFree(b->host);
+    delete b;
+    return NTT_EDEVICE;
+  }
+  *out = b;
+  return NTT_OK;
+}
+
+ntt_status ntt_batch_destroy(ntt_batch* b) {
+  if (!b) return NTT_EINVAL_POINTER;
+  if (b->pending) (void)hipEventSynchronize(b->done);
+  if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  (void)hipEventDestroy(b->done);
+  (void)hipFree(b->dev);
+  (void)hipHostFree(b->host);
+  delete b;
+  return NTT_OK;
+}
+
+ntt_status ntt_batch_set_grid(ntt_batch* b, int workgroups) {
+  if (!b) return NTT_EINVAL_POINTER;
+  if (workgroups < 0 || workgroups > (1 << 20)) return NTT_EINVAL_COUNT;
+  if (b->graph_exec && workgroups != b->grid) {   // the captured launch has a fixed grid
+    (void)hipGraphExecDestroy(b->graph_exec);
+    (void)hipGraphDestroy(b->graph);
+    b->graph_exec = nullptr;
+    b->graph = nullptr;
+  }
+  b->grid = workgroups;
+  return NTT_OK;
+}
+
+ntt_status ntt_batch_run(ntt_batch* b, const ntt_batch_item* items, size_t count, ntt_stream_t stream) {
+  if (!b || (!items && count)) return NTT_EINVAL_POINTER;
+  if (count > b->capacity) return NTT_EINVAL_COUNT;
+  if (count == 0) return NTT_OK;
+  size_t n = 0;
+  ntt_status st = batch_prepare(b, items, count, &n);
+  if (st) return st;
+  st = batch_enqueue(b, batch_grid(b, n), (hipStream_t)stream);
+  if (st) return st;
+  if (hipEventRecord(b->done, (hipStream_t)stream) != hipSuccess) return NTT_EDEVICE;
+  b->pending = true;
+  return NTT_OK;
+}
+
+ntt_status ntt_batch_run_graph(ntt_batch* b, const ntt_batch_item* items, size_t count, ntt_stream_t stream) {
+  if (!b || (!items && count)) return NTT_EINVAL_POINTER;
+  if (count > b->capacity) return NTT_EINVAL_COUNT;
+  if (count == 0) return NTT_OK;
+  size_t n = 0;
+  ntt_status st = batch_prepare(b, items, count, &n);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (!b->graph_exec) {
+    // capture once with the full-capacity grid; the kernel reads the count from device memory
+    const int grid = batch_grid(b, b->capacity);
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return NTT_EDEVICE;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipStreamDestroy(cap);
+      return NTT_EDEVICE;
+    }
+    st = batch_enqueue(b, grid, cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cap, &g);
+    (void)hipStreamDestroy(cap);
+    if (st) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess || !g) return NTT_EDEVICE;
+    if (hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return NTT_EDEVICE;
+    }
+    b->graph = g;
+  }
+  if (hipGraphLaunch(b->graph_exec, s) != hipSuccess) return NTT_EDEVICE;
+  if (hipEventRecord(b->done, s) != hipSuccess) return NTT_EDEVICE;
+  b->pending = true;
+  return NTT_OK;
+}
+
+}  // extern "C"

@@ -81,6 +81,16 @@ __device__ __forceinline__ u64 finish_mode(u64 v, u64 idx, const PassArgs& a, co
   return v;
 }
 
+// Same output step with the multiplier / accumulator given per item (mul
+// points at the item's first coefficient, i is the index inside the item).
+template <bool FWD, int MODE>
+__device__ __forceinline__ u64 finish_item(u64 v, const u64* mul, u64 i, const PlanView& pv) {
+  if (FWD && MODE == kOutMul) return barrett_mulmod<4>(v, mul[i], pv.q, pv.q2, pv.bk, pv.qbits);
+  if (!FWD && MODE == kOutAcc) return csub(mul[i] + csub(v, pv.q), pv.q);
+  if (MODE == kOutCanon) return FWD ? reduce4(v, pv.q, pv.q2) : csub(v, pv.q);
+  return v;
+}
+
 // Compiler-level fence: keeps the scheduler from hoisting the next stage's
 // twiddle loads above the current stage (which would blow up register use).
 __device__ __forceinline__ void stage_fence() { __asm__ volatile("" ::: "memory"); }

@@ -1,0 +1,208 @@
+// Single-pass transform of one limb held by one workgroup (N <= 2^14), as a
+// device-side building block: used by the single-pass kernel and by the
+// persistent batch kernel.  See ntt_onchip.hip for the design notes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <type_traits>
+
+#include "internal.h"
+#include "modarith.h"
+#include "ntt_common.h"
+
+namespace nttamd {
+
+template <bool FWD, int LOGN, int LOGR, bool SPLIT>
+struct OnChip {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int R = 1 << LOGR;
+  static constexpr int NT = N >> LOGR;
+  static constexpr int LDSW = N + (N >> LOGR);
+  // transposed sub-tables are laid out for onchip_logr(LOGN) coefficients per thread
+  static constexpr int PERM_TOP = LOGR == onchip_logr(LOGN) ? onchip_perm_top(FWD, LOGN) : -1;
+  static constexpr int TB = 2;                      // twiddle pairs per prefetch block
+  using G = Geo<FWD, LOGN, LOGR>;
+  using W = typename std::conditional<SPLIT, u32, u64>::type;
+
+  template <int r>
+  __device__ static __forceinline__ u32 rho(u32 t, int j) {
+    constexpr int lo = G::lo(r);
+    return ((t >> lo) << (lo + LOGR)) | ((u32)j << lo) | (t & ((1u << lo) - 1u));
+  }
+  __device__ static __forceinline__ u32 row(u32 r) { return r + (r >> LOGR); }
+
+  // Padded LDS row of element j of thread t in round r, split into a per-thread
+  // base and a compile-time offset of j.  With rho = hi | (j << lo) | lp
+  // (hi a multiple of 2^(lo+LOGR), lp < 2^lo), rho >> LOGR is exactly
+  // (hi >> LOGR) + (lp >> LOGR) + (j << lo >> LOGR) for lo >= LOGR, and
+  // (hi >> LOGR) + (j >> (LOGR - lo)) for lo < LOGR.
+  template <int r>
+  __device__ static __forceinline__ u32 row_base(u32 t) {
+    constexpr int lo = G::lo(r);
+    const u32 hi = (t >> lo) << (lo + LOGR);
+    const u32 lp = t & ((1u << lo) - 1u);
+    return hi + (hi >> LOGR) + lp + (lo >= LOGR ? (lp >> LOGR) : 0u);
+  }
+  template <int r>
+  static constexpr u32 row_off(int j) {
+    constexpr int lo = G::lo(r);
+    return ((u32)j << lo) + (lo >= LOGR ? ((u32)j << (lo - LOGR)) : ((u32)j >> (LOGR - lo)));
+  }
+  // Padded LDS row of tile element j * NT + t (the coalesced memory order).
+  __device__ static __forceinline__ u32 lin_row(u32 t, int j) {
+    if constexpr (LOGN >= 2 * LOGR) return (u32)j * (NT + (NT >> LOGR)) + t + (t >> LOGR);
+    else return row((u32)j * NT + t);
+  }
+
+  // Moves the thread's coefficients between two register layouts through LDS;
+  // ROW_OUT(j) / ROW_IN(j) give the padded LDS rows written / read for element j.
+  template <typename FO, typename FI>
+  __device__ static __forceinline__ void shuffle(W* lds, u64 (&x)[R], FO row_out, FI row_in) {
+    __syncthreads();
+    if constexpr (!SPLIT) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) lds[row_out(j)] = x[j];
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < R; ++j) x[j] = lds[row_in(j)];
+    } else {
+#pragma unroll
+      for (int j = 0; j < R; ++j) lds[row_out(j)] = lo32(x[j]);
+      __syncthreads();
+      u32 nl[R];
+#pragma unroll
+      for (int j = 0; j < R; ++j) nl[j] = lds[row_in(j)];
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < R; ++j) lds[row_out(j)] = hi32(x[j]);
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < R; ++j) x[j] = ((u64)lds[row_in(j)] << 32) | nl[j];
+    }
+  }
+
+  // twiddle pair u of the stage on local bit `bit` in round r for thread t
+  template <int r>
+  __device__ static __forceinline__ ulonglong2 twiddle(const PlanView& pv, u32 t, int bit, int u) {
+    constexpr int lo = G::lo(r);
+    if (lo == 0 && bit <= PERM_TOP) return pv.twp[(N >> (bit + 1)) + (u32)u * NT + t];
+    return pv.tw[((N + rho<r>(t, 0)) >> (bit + 1)) + (u32)u];
+  }
+
+  // number of twiddle blocks of stage s in round r
+  template <int r>
+  static constexpr int nblocks(int s) {
+    return ((R >> ((FWD ? (G::first_bit(r) - s) : (G::first_bit(r) + s)) - G::lo(r) + 1)) + TB - 1) / TB;
+  }
+  // first step (global block counter) of stage s in round r
+  template <int r>
+  static constexpr int first_step(int s) {
+    int n = 0;
+    for (int i = 0; i < s; ++i) n += nblocks<r>(i);
+    return n;
+  }
+
+  template <int r>
+  __device__ static __forceinline__ void stages(u64 (&x)[R], u32 t, const PlanView& pv) {
+    constexpr int lo = G::lo(r);
+    constexpr int NS = G::nst(r);
+    // two twiddle buffers used alternately by consecutive blocks (ping-pong on
+    // the compile-time block counter, so no register copies are needed)
+    ulonglong2 buf[2][TB];
+    auto load_block = [&](ulonglong2 (&dst)[TB], int s, int blk) {
+      const int bit = FWD ? (G::first_bit(r) - s) : (G::first_bit(r) + s);
+      const int p = bit - lo;
+      const int n = R >> (p + 1);
+      const bool fused_last = !FWD && bit == LOGN - 1;
+      if (fused_last) return;
+#pragma unroll
+      for (int i = 0; i < TB; ++i)
+        if (blk * TB + i < n) dst[i] = twiddle<r>(pv, t, bit, blk * TB + i);
+    };
+    load_block(buf[0], 0, 0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int bit = FWD ? (G::first_bit(r) - s) : (G::first_bit(r) + s);
+      const int p = bit - lo;
+      const int n = R >> (p + 1);
+      const int nb = (n + TB - 1) / TB;
+      const bool fused_last = !FWD && bit == LOGN - 1;
+#pragma unroll
+      for (int blk = 0; blk < nb; ++blk) {
+        const int step = first_step<r>(s) + blk;
+        ulonglong2 (&cur)[TB] = buf[step & 1];
+        ulonglong2 (&nxt)[TB] = buf[(step + 1) & 1];
+        if (blk + 1 < nb) load_block(nxt, s, blk + 1);
+        else if (s + 1 < NS) load_block(nxt, s + 1, 0);
+#pragma unroll
+        for (int i = 0; i < TB; ++i) {
+          const int u = blk * TB + i;
+          if (u >= n) continue;
+#pragma unroll
+          for (int m = 0; m < (1 << p); ++m) {
+            const int j = (u << (p + 1)) | m;
+            const int j2 = j | (1 << p);
+            if (FWD) harvey_fwd(x[j], x[j2], cur[i].x, cur[i].y, pv.q2, pv.nq);
+            else if (fused_last) harvey_inv_last(x[j], x[j2], pv.ninv, pv.ninv_p, pv.wn, pv.wn_p, pv.q2, pv.nq);
+            else harvey_inv(x[j], x[j2], cur[i].x, cur[i].y, pv.q2, pv.nq);
+          }
+        }
+        stage_fence();
+      }
+    }
+  }
+
+  template <int r>
+  __device__ static __forceinline__ void run(W* lds, u64 (&x)[R], u32 t, const PlanView& pv) {
+    stages<r>(x, t, pv);
+    if constexpr (r + 1 < G::NR) {
+      const u32 bo = row_base<r>(t), bi = row_base<r + 1>(t);
+      shuffle(lds, x, [&](int j) { return bo + row_off<r>(j); }, [&](int j) { return bi + row_off<r + 1>(j); });
+      run<r + 1>(lds, x, t, pv);
+    }
+  }
+};
+
+// Transforms one limb: reads `in` (N coefficients), writes `out`; the output
+// step applies MODE with the per-item multiplier / accumulator `mul`.
+template <bool FWD, int LOGN, int LOGR, bool SPLIT, int MODE>
+__device__ __forceinline__ void onchip_body(const PlanView& pv, const u64* in, u64* out, const u64* mul,
+                                            typename OnChip<FWD, LOGN, LOGR, SPLIT>::W* lds, bool nt_load) {
+  using K = OnChip<FWD, LOGN, LOGR, SPLIT>;
+  constexpr int R = K::R;
+  constexpr int NT = K::NT;
+  constexpr int RL = K::G::NR - 1;
+  constexpr bool direct_in = K::G::lo(0) >= 4 || LOGN - LOGR < 4;
+  constexpr bool direct_out = K::G::lo(RL) >= 4 || LOGN - LOGR < 4;
+  const u32 t = threadIdx.x;
+  u64 x[R];
+  if constexpr (direct_in) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const u64* p = &in[K::template rho<0>(t, j)];
+      x[j] = nt_load ? __builtin_nontemporal_load(p) : *p;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const u64* p = &in[(u32)j * NT + t];
+      x[j] = nt_load ? __builtin_nontemporal_load(p) : *p;
+    }
+    const u32 bi = K::template row_base<0>(t);
+    K::shuffle(lds, x, [&](int j) { return K::lin_row(t, j); }, [&](int j) { return bi + K::template row_off<0>(j); });
+  }
+
+  K::template run<0>(lds, x, t, pv);
+
+  if constexpr (!direct_out) {
+    const u32 bo = K::template row_base<RL>(t);
+    K::shuffle(lds, x, [&](int j) { return bo + K::template row_off<RL>(j); }, [&](int j) { return K::lin_row(t, j); });
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const u32 i = direct_out ? K::template rho<RL>(t, j) : (u32)j * NT + t;
+    out[i] = finish_item<FWD, MODE>(x[j], mul, i, pv);
+    if ((j & 7) == 7) stage_fence();
+  }
+}
+
+}  // namespace nttamd

@@ -354,3 +354,115 @@ def test_poly_mul_acc_rns(nt, logN, L, B):
                 ab = oracle.negacyclic_mul_at(a[s], b[s], idx, q)
                 ref = oracle.eltwise_add(oracle.eltwise_add(acc0[s][idx], ab, q), ab, q)
                 assert np.array_equal(acc[s][idx], ref)
+
+
+# ---------------------------------------------------------------- uneven batches (persistent launch)
+
+def _batch_case(nt, seed, specs):
+    """specs: list of (op, logN, q).  Returns (items, host inputs, device tensors)."""
+    tasks, host = [], []
+    for k, (op, logN, q) in enumerate(specs):
+        N = 1 << logN
+        a = uniform_mod(unit_seed(seed, k, 1), N, q)
+        b = uniform_mod(unit_seed(seed, k, 2), N, q) if op == nt.BATCH_PRODUCT else None
+        da = to_dev(a)
+        db = to_dev(b) if b is not None else None
+        out = empty_dev(N)
+        tmp = empty_dev(N) if (op == nt.BATCH_PRODUCT and logN > 14) else None
+        tasks.append((op, out, da, db, tmp, N, q))
+        host.append((op, logN, q, a, b))
+    return tasks, host
+
+
+def _check_batch_outputs(nt, tasks, host):
+    for (op, out, _, _, _, N, q), (_, logN, _, a, b) in zip(tasks, host):
+        got = from_dev(out)
+        psi = oracle.min_root(N, q)
+        full = N <= 2048
+        idx = None if full else _sample_idx(N, 90 + logN, 12)
+        if op == nt.BATCH_PRODUCT:
+            ref = oracle.negacyclic_mul(a, b, q) if full else oracle.negacyclic_mul_at(a, b, idx, q)
+            assert np.array_equal(got if full else got[idx], ref), ("product", logN)
+            continue
+        fwd = op in (nt.BATCH_FWD, nt.BATCH_FWD_LAZY)
+        bound = {nt.BATCH_FWD: 1, nt.BATCH_FWD_LAZY: 4, nt.BATCH_INV: 1, nt.BATCH_INV_LAZY: 2}[op]
+        assert np.all(got < np.uint64(bound * q))
+        if fwd:
+            ref = oracle.ntt_forward(a, q, psi) if full else oracle.ntt_forward_at(a, idx, q, psi)
+        else:
+            ref = oracle.ntt_inverse(a, q, psi) if full else oracle.ntt_inverse_at(a, idx, q, psi)
+        assert np.array_equal((got if full else got[idx]) % np.uint64(q), ref), (op, logN)
+        if fwd and bound == 4:         # lazy forward outputs equal the Harvey model
+            assert np.array_equal(got, oracle.harvey_forward(a, q, psi, 4)), logN
+
+
+def test_batch_uneven_mixed_ops(nt):
+    serving = PRIMES["serving"]["moduli"]
+    specs = []
+    ops = [nt.BATCH_FWD_LAZY, nt.BATCH_FWD, nt.BATCH_INV_LAZY, nt.BATCH_INV, nt.BATCH_PRODUCT]
+    k = 0
+    for logN in range(10, 18):
+        for op in ops:
+            specs.append((op, logN, serving[k % len(serving)]))
+            k += 1
+    tasks, host = _batch_case(nt, 100, specs)
+    batch = nt.Batch(64)
+    batch.run(tasks)
+    _check_batch_outputs(nt, tasks, host)
+    # the same tasks through the per-call entry points give the same words
+    for (op, out, da, db, tmp, N, q) in tasks[:10]:
+        ref = empty_dev(N)
+        if op == nt.BATCH_FWD_LAZY:
+            nt.ntt_forward(ref, da, N, q, 1, 4)
+        elif op == nt.BATCH_FWD:
+            nt.ntt_forward(ref, da, N, q, 1, 1)
+        elif op == nt.BATCH_INV_LAZY:
+            nt.ntt_inverse(ref, da, N, q, 1, 2)
+        elif op == nt.BATCH_INV:
+            nt.ntt_inverse(ref, da, N, q, 1, 1)
+        else:
+            continue
+        if op != nt.BATCH_INV_LAZY:      # lazy inverse representatives may differ between schedules
+            assert np.array_equal(from_dev(ref), from_dev(out)), (op, N)
+    batch.close()
+
+
+def test_batch_graph_replays(nt):
+    moduli = PRIMES["uneven"]["moduli"]
+    specs1 = [(nt.BATCH_FWD_LAZY, 12 + (k % 4), moduli[k % 16]) for k in range(40)]
+    specs2 = [(nt.BATCH_INV, 12 + ((k + 1) % 4), moduli[(3 * k) % 16]) for k in range(23)]
+    t1, h1 = _batch_case(nt, 110, specs1)
+    t2, h2 = _batch_case(nt, 111, specs2)
+    batch = nt.Batch(64)
+    batch.run(t1, graph=True)
+    _check_batch_outputs(nt, t1, h1)
+    first = [from_dev(t[1]).copy() for t in t1]
+    import torch
+    for rep in range(3):
+        for t in t1:
+            t[1].zero_()
+        torch.cuda.synchronize()
+        batch.run(t1, graph=True)                 # replay: same graph, same descriptors
+        torch.cuda.synchronize()
+        for t, f in zip(t1, first):
+            assert np.array_equal(from_dev(t[1]), f), rep
+        batch.run(t2, graph=True)                 # replay with a different, smaller batch
+        torch.cuda.synchronize()
+        _check_batch_outputs(nt, t2, h2)
+    batch.close()
+
+
+def test_batch_rejects_bad_items(nt):
+    batch = nt.Batch(4)
+    d = empty_dev(1024)
+    q = PRIMES["single_1024"]["moduli"][0]
+    with pytest.raises(nt.NttError) as e:
+        batch.run([(nt.BATCH_PRODUCT, d, d, None, None, 1024, q)])
+    assert e.value.status == nt.NTT_EINVAL_POINTER
+    with pytest.raises(nt.NttError) as e:
+        batch.run([(nt.BATCH_FWD, d, d, None, None, 512, q)])
+    assert e.value.status == nt.NTT_EINVAL_DEGREE
+    with pytest.raises(nt.NttError) as e:
+        batch.run([(nt.BATCH_FWD, d, d, None, None, 1024, q)] * 5)
+    assert e.value.status == nt.NTT_EINVAL_COUNT
+    batch.close()
