@@ -106,6 +106,69 @@ def time_large_ring(nt, torch, primes, reps=20):
     return out
 
 
+def time_uneven_batch(nt, torch, primes, reps=10):
+    """256 RNS polynomials, N uniform in {2^12..2^15}, limb counts uniform in [2, 16], 50-bit
+    primes (limb l uses the l-th prime of the pool): forward (1 -> 4) and inverse (1 -> 1) of
+    every limb as one persistent launch (plain and hipGraph-replayed, grid autotuned) versus
+    one launch per limb-transform."""
+    from synthetic import uniform_int, uniform_mod, unit_seed
+    pool = primes["uneven"]["moduli"]
+    P = 256
+    logNs = uniform_int(unit_seed(4, 0), P, 12, 15)
+    Ls = uniform_int(unit_seed(4, 1), P, 2, 16)
+    dev = torch.device("cuda:0")
+    limbs = [(int(logNs[p]), pool[l]) for p in range(P) for l in range(int(Ls[p]))]
+    total = sum(1 << n for n, _ in limbs)
+    src = torch.empty(total, dtype=torch.int64, device=dev)
+    dst = torch.empty(total, dtype=torch.int64, device=dev)
+    off, views = 0, []
+    host = np.empty(total, dtype=np.uint64)
+    for k, (n, q) in enumerate(limbs):
+        N = 1 << n
+        host[off:off + N] = uniform_mod(unit_seed(5, k, q), N, q)
+        views.append((src[off:off + N], dst[off:off + N], N, q))
+        off += N
+    src.copy_(torch.from_numpy(host.view(np.int64)))
+    stream = torch.cuda.current_stream()
+    batch = nt.Batch(len(limbs))
+    res = {"limbs": len(limbs), "coefficients": total}
+    plans = {(N, q) for _, _, N, q in views}
+    alg = 16 * total + 16 * sum(N for N, _ in plans)
+    for name, op in (("fwd", nt.BATCH_FWD_LAZY), ("inv", nt.BATCH_INV)):
+        items, cnt = nt.Batch.make_items([(op, d, s_, None, None, N, q) for s_, d, N, q in views])
+        res[name + "_grid"] = batch.autotune(items, cnt, stream=stream)
+        for mode in ("batched", "graph"):
+            batch.run(items, cnt, stream=stream, graph=(mode == "graph"))
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                batch.run(items, cnt, stream=stream, graph=(mode == "graph"))
+            e1.record(stream)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / reps
+            res["%s_%s_us" % (name, mode)] = round(us, 1)
+            res["%s_%s_limb_ntts_per_s" % (name, mode)] = round(len(limbs) / (us * 1e-6), 1)
+            res["%s_%s_hbm_frac" % (name, mode)] = round(alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+        # plain form: one launch per limb-transform
+        fn = (lambda s_, d, N, q: nt.ntt_forward(d, s_, N, q, 1, 4, stream=stream)) if name == "fwd" else \
+             (lambda s_, d, N, q: nt.ntt_inverse(d, s_, N, q, 1, 1, stream=stream))
+        for v in views:
+            fn(*v)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for v in views:
+            fn(*v)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3
+        res["%s_per_call_us" % name] = round(us, 1)
+        res["%s_per_call_limb_ntts_per_s" % name] = round(len(limbs) / (us * 1e-6), 1)
+    batch.close()
+    return res
+
+
 def time_single_1024(nt, torch, primes, reps=200):
     """Per-call latency of one forward and one inverse NTT at N = 1024 (single limb)."""
     p1 = primes["single_1024"]
@@ -223,6 +286,7 @@ def main():
         torch.cuda.empty_cache()
         out["large_ring_n65536_l32"] = time_large_ring(nt, torch, load_primes())
         out["single_n1024"] = time_single_1024(nt, torch, load_primes())
+        out["uneven_batch_256polys"] = time_uneven_batch(nt, torch, load_primes())
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, moduli, psis, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -257,6 +257,13 @@ ntt_status ntt_batch_destroy(ntt_batch* batch);
 ntt_status ntt_batch_set_grid(ntt_batch* batch, int workgroups);
 ntt_status ntt_batch_run(ntt_batch* batch, const ntt_batch_item* items, size_t count, ntt_stream_t stream);
 ntt_status ntt_batch_run_graph(ntt_batch* batch, const ntt_batch_item* items, size_t count, ntt_stream_t stream);
+/* Times the persistent launch of this batch with one, one and a half and two
+ * workgroups per CU and keeps the fastest grid for the context (the chosen
+ * count in *chosen, may be NULL).  Runs the batch several times, so every
+ * task must have out != in (NTT_EALIAS otherwise); outputs end up holding the
+ * batch's result.  Synchronises `stream`. */
+ntt_status ntt_batch_autotune(ntt_batch* batch, const ntt_batch_item* items, size_t count, ntt_stream_t stream,
+                              int* chosen);
 
 /* ---------------------------------------------------------------------------
  * Autotuning (the paper's Section 4 remark that the best implementation could

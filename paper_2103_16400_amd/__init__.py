@@ -50,6 +50,7 @@ _SIGS = {
     "ntt_batch_set_grid": (_ST, [_P, ctypes.c_int]),
     "ntt_batch_run": (_ST, [_P, _P, ctypes.c_size_t, _P]),
     "ntt_batch_run_graph": (_ST, [_P, _P, ctypes.c_size_t, _P]),
+    "ntt_batch_autotune": (_ST, [_P, _P, ctypes.c_size_t, _P, ctypes.POINTER(ctypes.c_int)]),
     "ntt_autotune": (_ST, [_U64, _P, _U64, _U64, _P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "ntt_set_variant": (_ST, [_U64, _U64, ctypes.c_int, ctypes.c_int]),
 }
@@ -277,6 +278,13 @@ class Batch:
             arr[k].q = q
             arr[k].op = op
         return arr, len(tasks)
+
+    def autotune(self, items, count=None, stream=None):
+        if not isinstance(items, ctypes.Array):
+            items, count = self.make_items(items)
+        g = ctypes.c_int(0)
+        _check(_lib.ntt_batch_autotune(self._h, items, count, _stream(stream), ctypes.byref(g)), "ntt_batch_autotune")
+        return g.value
 
     def run(self, items, count=None, stream=None, graph=False):
         if not isinstance(items, ctypes.Array):

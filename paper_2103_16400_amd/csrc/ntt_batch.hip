@@ -335,4 +335,42 @@ ntt_status ntt_batch_run_graph(ntt_batch* b, const ntt_batch_item* items, size_t
   return NTT_OK;
 }
 
+ntt_status ntt_batch_autotune(ntt_batch* b, const ntt_batch_item* items, size_t count, ntt_stream_t stream,
+                              int* chosen) {
+  if (!b || !items) return NTT_EINVAL_POINTER;
+  if (count == 0 || count > b->capacity) return NTT_EINVAL_COUNT;
+  for (size_t i = 0; i < count; ++i)
+    if (items[i].out == items[i].in) return NTT_EALIAS;   // every trial must see the same inputs
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int cand[3] = {cus, (3 * cus) / 2, 2 * cus};
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return NTT_EDEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return NTT_EDEVICE; }
+  const int saved = b->grid;
+  int best = saved;
+  float best_ms = 1e30f;
+  ntt_status st = NTT_OK;
+  for (int c = 0; c < 3 && st == NTT_OK; ++c) {
+    b->grid = cand[c];
+    st = ntt_batch_run(b, items, count, stream);                 // warm-up
+    if (st) break;
+    if (hipEventRecord(e0, s) != hipSuccess) { st = NTT_EDEVICE; break; }
+    for (int r = 0; r < 3 && st == NTT_OK; ++r) st = ntt_batch_run(b, items, count, stream);
+    if (st) break;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { st = NTT_EDEVICE; break; }
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best_ms) { best_ms = ms; best = cand[c]; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->grid = saved;
+  if (st) return st;
+  st = ntt_batch_set_grid(b, best);
+  if (chosen) *chosen = best;
+  return st;
+}
+
 }  // extern "C"
