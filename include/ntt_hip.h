@@ -55,6 +55,7 @@ typedef int ntt_status;
 #define NTT_ENOMEM (-9)          /* device or host allocation failed                   */
 #define NTT_ENOTFOUND (-10)      /* unknown handle / nothing to report                 */
 #define NTT_EBUSY (-11)          /* admission refused: budget or queue full            */
+#define NTT_ETIMEDOUT (-12)      /* a wait ended before the awaited work completed     */
 
 /* Largest ring degree and limb count the kernels are built for. */
 #define NTT_MAX_LOG_DEGREE 17
@@ -280,6 +281,121 @@ ntt_status ntt_batch_autotune(ntt_batch* batch, const ntt_batch_item* items, siz
 ntt_status ntt_autotune(uint64_t N, const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
                         ntt_stream_t stream, int* choice_fwd, int* choice_inv);
 ntt_status ntt_set_variant(uint64_t N, uint64_t num_items, int forward, int variant);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of negacyclic polynomial products.
+ *
+ * A request asks for c = a * b in Z_q[X]/(X^N + 1) for each of its L RNS
+ * limbs (the forward / multiply / inverse sequence of the paper's Section 4
+ * product listing; the limbs are independent, Section 5).  The server is a
+ * native scheduler thread on the device current at creation:
+ *   - arrival: a request counts from its arrival time (ntt_server_now_ns
+ *     clock; 0 = when submitted).  A request submitted ahead of its arrival
+ *     time stays invisible to the scheduler until that time, so a load
+ *     generator can hand over a pre-drawn open-loop schedule;
+ *   - admission: arrived requests are admitted strictly in arrival order
+ *     while the server's device arena (hbm_budget bytes, allocated once at
+ *     creation) has room for the request's footprint: its result,
+ *     L * N * 8 bytes, plus for N > 2^14 (and for every N in per-limb mode) a
+ *     workspace of the same size (one limb's worth, N * 8, in per-limb mode).
+ *     A request that does not fit waits (backpressure) until earlier requests
+ *     complete and are released;
+ *   - NTT_SERVE_BATCHED: every admitted request not yet launched goes into
+ *     the next persistent batch launch (one task per limb product, largest
+ *     first), with up to `streams` launches in flight on separate streams, so
+ *     requests that arrive while others run join the next launch and its work
+ *     overlaps the tail of the running one;
+ *   - NTT_SERVE_FIFO: each request alone, in arrival order on one stream,
+ *     as three launches over its limbs (forward, forward fused with the
+ *     multiply, inverse);
+ *   - NTT_SERVE_FIFO_PER_LIMB: each request alone, in arrival order on one
+ *     stream, one launch per limb transform and per limb multiply (the plain
+ *     per-call form);
+ *   - completion: a request is done when the launch that holds its last limb
+ *     has completed on the device; its result (canonical, layout [L][N]) is
+ *     then readable at info.result until ntt_server_release.
+ * Every mode gives bit-identical results: each limb product is computed by
+ * the same exact arithmetic whatever else shares the launch.
+ *
+ * ntt_server_create: config may be NULL (all defaults).  hbm_budget 0 = 16 GiB;
+ *   streams 0 = 2 (at most 4); max_batch_tasks 0 = 4096 (at least 64);
+ *   max_queue 0 = 2^20 requests submitted but not yet admitted.
+ *   release_on_completion != 0 returns a request's arena space as soon as it
+ *   completes (for load generation: the result is then not kept).
+ * ntt_server_submit: validates and queues; plans for new (N, q) are built on
+ *   the calling thread, which must have the server's device current
+ *   (NTT_EDEVICE otherwise).  Errors: NTT_EINVAL_POINTER (null a, b, moduli,
+ *   ticket), NTT_EINVAL_DEGREE (N not a power of two in [2^10, 2^17]),
+ *   NTT_EINVAL_COUNT (num_limbs outside [1, 64]), NTT_EINVAL_MODULUS (a limb
+ *   modulus not prime, not 1 mod 2N, or >= 2^62), NTT_ENOMEM (the footprint
+ *   exceeds the whole budget, so the request could never be admitted),
+ *   NTT_EBUSY (queue full, or the server is shutting down).  a and b are
+ *   device arrays [L][N] with limb l's values in [0, q_l); they are read-only
+ *   and must stay valid until the request completes.
+ * ntt_server_poll / ntt_server_query: state of one / several tickets
+ *   (NTT_ENOTFOUND for an unknown or released ticket).
+ * ntt_server_wait: blocks until the ticket completes or fails
+ *   (NTT_ETIMEDOUT after timeout_ns; < 0 waits without limit).
+ * ntt_server_drain: blocks until every submitted request has completed or
+ *   failed (NTT_ETIMEDOUT after timeout_ns; < 0 waits without limit).
+ * ntt_server_read: enqueues on `stream` a copy of a completed request's
+ *   result into dst (device, L * N words); NTT_EBUSY before completion, the
+ *   request's own status if it failed, NTT_ENOTFOUND without a kept result.
+ * ntt_server_release: frees a completed request's result and record
+ *   (NTT_EBUSY while it is still queued or running).
+ * ntt_server_destroy: requests not yet launched fail with NTT_EBUSY, launches
+ *   in flight are waited for, then the arena and streams are freed.
+ */
+typedef struct ntt_server ntt_server;
+#define NTT_SERVE_BATCHED 0u
+#define NTT_SERVE_FIFO 1u
+#define NTT_SERVE_FIFO_PER_LIMB 2u
+typedef struct {
+  uint64_t hbm_budget;
+  uint32_t mode;
+  uint32_t streams;
+  uint32_t max_batch_tasks;
+  uint32_t max_queue;
+  uint32_t release_on_completion;
+  uint32_t use_graph;       /* nonzero: batched launches replay a captured hipGraph */
+} ntt_server_config;
+typedef struct {
+  uint64_t N;
+  uint64_t num_limbs;
+  const uint64_t* moduli;   /* host array of num_limbs primes, copied at submission */
+  const uint64_t* a;
+  const uint64_t* b;
+  int64_t arrival_ns;
+} ntt_request;
+#define NTT_REQ_WAITING 0u    /* submitted, not arrived or not admitted */
+#define NTT_REQ_ADMITTED 1u   /* arena space reserved, not launched */
+#define NTT_REQ_RUNNING 2u
+#define NTT_REQ_DONE 3u
+#define NTT_REQ_FAILED 4u
+typedef struct {
+  uint32_t state;
+  ntt_status status;        /* NTT_OK, or why the request failed */
+  uint64_t* result;         /* device [L][N], valid in state DONE until release (NULL otherwise) */
+  int64_t arrival_ns, admit_ns, launch_ns, done_ns;
+} ntt_request_info;
+typedef struct {
+  uint64_t submitted, rejected, completed, failed;
+  uint64_t launches, tasks;
+  uint64_t waiting, in_flight;
+  uint64_t arena_bytes, arena_in_use, arena_peak;
+  uint64_t deferred;        /* admissions postponed for lack of arena space */
+} ntt_server_stats;
+ntt_status ntt_server_create(ntt_server** server, const ntt_server_config* config);
+ntt_status ntt_server_submit(ntt_server* server, const ntt_request* request, uint64_t* ticket);
+ntt_status ntt_server_poll(ntt_server* server, uint64_t ticket, ntt_request_info* info);
+ntt_status ntt_server_query(ntt_server* server, const uint64_t* tickets, size_t count, ntt_request_info* infos);
+ntt_status ntt_server_wait(ntt_server* server, uint64_t ticket, int64_t timeout_ns, ntt_request_info* info);
+ntt_status ntt_server_drain(ntt_server* server, int64_t timeout_ns);
+ntt_status ntt_server_read(ntt_server* server, uint64_t ticket, uint64_t* dst, ntt_stream_t stream);
+ntt_status ntt_server_release(ntt_server* server, uint64_t ticket);
+ntt_status ntt_server_stats_get(ntt_server* server, ntt_server_stats* stats);
+int64_t ntt_server_now_ns(void);
+ntt_status ntt_server_destroy(ntt_server* server);
 
 #ifdef __cplusplus
 }

@@ -51,6 +51,17 @@ _SIGS = {
     "ntt_batch_run": (_ST, [_P, _P, ctypes.c_size_t, _P]),
     "ntt_batch_run_graph": (_ST, [_P, _P, ctypes.c_size_t, _P]),
     "ntt_batch_autotune": (_ST, [_P, _P, ctypes.c_size_t, _P, ctypes.POINTER(ctypes.c_int)]),
+    "ntt_server_create": (_ST, [ctypes.POINTER(_P), _P]),
+    "ntt_server_submit": (_ST, [_P, _P, ctypes.POINTER(_U64)]),
+    "ntt_server_poll": (_ST, [_P, _U64, _P]),
+    "ntt_server_query": (_ST, [_P, _P, ctypes.c_size_t, _P]),
+    "ntt_server_wait": (_ST, [_P, _U64, ctypes.c_int64, _P]),
+    "ntt_server_drain": (_ST, [_P, ctypes.c_int64]),
+    "ntt_server_read": (_ST, [_P, _U64, _P, _P]),
+    "ntt_server_release": (_ST, [_P, _U64]),
+    "ntt_server_stats_get": (_ST, [_P, _P]),
+    "ntt_server_now_ns": (ctypes.c_int64, []),
+    "ntt_server_destroy": (_ST, [_P]),
     "ntt_autotune": (_ST, [_U64, _P, _U64, _U64, _P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "ntt_set_variant": (_ST, [_U64, _U64, ctypes.c_int, ctypes.c_int]),
 }
@@ -291,6 +302,109 @@ class Batch:
             items, count = self.make_items(items)
         fn = _lib.ntt_batch_run_graph if graph else _lib.ntt_batch_run
         _check(fn(self._h, items, count, _stream(stream)), "ntt_batch_run_graph" if graph else "ntt_batch_run")
+
+
+class ServerConfig(ctypes.Structure):
+    """ntt_server_config of include/ntt_hip.h."""
+    _fields_ = [("hbm_budget", _U64), ("mode", ctypes.c_uint32), ("streams", ctypes.c_uint32),
+                ("max_batch_tasks", ctypes.c_uint32), ("max_queue", ctypes.c_uint32),
+                ("release_on_completion", ctypes.c_uint32), ("use_graph", ctypes.c_uint32)]
+
+
+class Request(ctypes.Structure):
+    """ntt_request of include/ntt_hip.h."""
+    _fields_ = [("N", _U64), ("num_limbs", _U64), ("moduli", ctypes.POINTER(_U64)), ("a", _P), ("b", _P),
+                ("arrival_ns", ctypes.c_int64)]
+
+
+class RequestInfo(ctypes.Structure):
+    """ntt_request_info of include/ntt_hip.h."""
+    _fields_ = [("state", ctypes.c_uint32), ("status", ctypes.c_int), ("result", _P), ("arrival_ns", ctypes.c_int64),
+                ("admit_ns", ctypes.c_int64), ("launch_ns", ctypes.c_int64), ("done_ns", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    """ntt_server_stats of include/ntt_hip.h."""
+    _fields_ = [(n, _U64) for n in ("submitted", "rejected", "completed", "failed", "launches", "tasks", "waiting",
+                                    "in_flight", "arena_bytes", "arena_in_use", "arena_peak", "deferred")]
+
+
+SERVE_BATCHED, SERVE_FIFO, SERVE_FIFO_PER_LIMB = 0, 1, 2
+REQ_WAITING, REQ_ADMITTED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3, 4
+
+
+def now_ns() -> int:
+    """The serving clock (monotonic, nanoseconds)."""
+    return _lib.ntt_server_now_ns()
+
+
+class Server:
+    """Continuous-batching server for negacyclic products (ntt_server_* of include/ntt_hip.h)."""
+
+    def __init__(self, hbm_budget=0, mode=SERVE_BATCHED, streams=0, max_batch_tasks=0, max_queue=0,
+                 release_on_completion=False, use_graph=False):
+        cfg = ServerConfig(hbm_budget, mode, streams, max_batch_tasks, max_queue, int(bool(release_on_completion)),
+                           int(bool(use_graph)))
+        h = _P()
+        _check(_lib.ntt_server_create(ctypes.byref(h), ctypes.byref(cfg)), "ntt_server_create")
+        self._h = h
+
+    def close(self):
+        if self._h:
+            _lib.ntt_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit_status(self, a, b, N, moduli, arrival_ns=0):
+        """Returns (status, ticket) without raising."""
+        mods = (_U64 * max(1, len(moduli)))(*[int(q) for q in moduli])
+        req = Request(N, len(moduli), mods, _ptr(a), _ptr(b), arrival_ns)
+        t = _U64(0)
+        st = _lib.ntt_server_submit(self._h, ctypes.byref(req), ctypes.byref(t))
+        return st, t.value
+
+    def submit(self, a, b, N, moduli, arrival_ns=0) -> int:
+        st, t = self.submit_status(a, b, N, moduli, arrival_ns)
+        _check(st, "ntt_server_submit")
+        return t
+
+    def poll(self, ticket) -> RequestInfo:
+        info = RequestInfo()
+        _check(_lib.ntt_server_poll(self._h, ticket, ctypes.byref(info)), "ntt_server_poll")
+        return info
+
+    def query(self, tickets):
+        n = len(tickets)
+        arr = (_U64 * max(1, n))(*tickets)
+        infos = (RequestInfo * max(1, n))()
+        _check(_lib.ntt_server_query(self._h, arr, n, infos), "ntt_server_query")
+        return infos[:n]
+
+    def wait(self, ticket, timeout_s=None) -> RequestInfo:
+        info = RequestInfo()
+        t = -1 if timeout_s is None else int(timeout_s * 1e9)
+        _check(_lib.ntt_server_wait(self._h, ticket, t, ctypes.byref(info)), "ntt_server_wait")
+        return info
+
+    def drain(self, timeout_s=None):
+        t = -1 if timeout_s is None else int(timeout_s * 1e9)
+        _check(_lib.ntt_server_drain(self._h, t), "ntt_server_drain")
+
+    def read(self, ticket, dst, stream=None):
+        _check(_lib.ntt_server_read(self._h, ticket, _ptr(dst), _stream(stream)), "ntt_server_read")
+
+    def release(self, ticket):
+        _check(_lib.ntt_server_release(self._h, ticket), "ntt_server_release")
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(_lib.ntt_server_stats_get(self._h, ctypes.byref(s)), "ntt_server_stats_get")
+        return {n: getattr(s, n) for n, _ in ServerStats._fields_}
 
 
 def shutdown():

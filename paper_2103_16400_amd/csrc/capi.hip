@@ -113,6 +113,7 @@ const char* ntt_status_string(ntt_status s) {
     case NTT_ENOMEM: return "out of memory";
     case NTT_ENOTFOUND: return "not found";
     case NTT_EBUSY: return "busy: admission refused";
+    case NTT_ETIMEDOUT: return "timed out";
     default: return "unknown status";
   }
 }

@@ -137,6 +137,9 @@ struct EltLaunch {
   hipStream_t stream;
 };
 ntt_status launch_eltwise_mult(const EltLaunch& l);
+// Persistent batch launch of already-resolved tasks (ntt_batch.hip); sorts them
+// largest first into the context's staging buffer.
+ntt_status batch_launch_tasks(ntt_batch* b, const BatchTask* tasks, size_t count, hipStream_t stream, bool graph);
 ntt_status launch_eltwise_add(const EltLaunch& l);
 
 }  // namespace nttamd

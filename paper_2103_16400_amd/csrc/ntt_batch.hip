@@ -30,19 +30,24 @@
 struct ntt_batch {
   int device;
   size_t capacity;                 // tasks
-  nttamd::BatchTask* host;         // pinned staging: tasks then the count
-  nttamd::BatchTask* dev;          // device copy
-  uint32_t* dev_count;             // task count (device)
-  uint32_t* dev_counter;           // claim counter (device)
+  unsigned char* host;             // pinned staging: count word (128-byte line), then the tasks
+  unsigned char* dev;              // device: claim counter (own line), count word, tasks
   hipEvent_t done;                 // completion of the last run (staging reuse)
   bool pending;
   int grid;                        // persistent workgroups (0: automatic)
   hipGraph_t graph;
   hipGraphExec_t graph_exec;
-  hipStream_t graph_stream;
 };
 
 namespace nttamd {
+
+// Staging layout: [0, 128) count word; tasks from byte 128.  The device copy
+// keeps the claim counter in its own line in front: counter at 0, staging
+// mirrored from byte 128.
+constexpr size_t kStageHead = 128;
+constexpr size_t kDevHead = 128;
+static BatchTask* staged_tasks(ntt_batch* b) { return reinterpret_cast<BatchTask*>(b->host + kStageHead); }
+static size_t stage_bytes(size_t count) { return kStageHead + count * sizeof(BatchTask); }
 
 constexpr int kBatchThreads = 512;
 constexpr int kBatchLdsWords32 = (1 << 14) + (1 << 14) / 32;   // 2^14 split exchange, 66 KiB
@@ -149,11 +154,17 @@ static uint64_t task_cost(uint32_t logN, uint32_t op) {
   return n * logN * (op == kBatchProduct ? 3 : 1);
 }
 
-ntt_status batch_prepare(ntt_batch* b, const ntt_batch_item* items, size_t count, size_t* out_count) {
+static ntt_status wait_staging(ntt_batch* b) {
   if (b->pending) {
     if (hipEventSynchronize(b->done) != hipSuccess) return NTT_EDEVICE;   // staging still in use
     b->pending = false;
   }
+  return NTT_OK;
+}
+
+ntt_status batch_prepare(ntt_batch* b, const ntt_batch_item* items, size_t count, size_t* out_count) {
+  ntt_status st0 = wait_staging(b);
+  if (st0) return st0;
   std::vector<std::pair<uint64_t, size_t>> order(count);
   for (size_t i = 0; i < count; ++i) {
     const ntt_batch_item& it = items[i];
@@ -190,7 +201,7 @@ ntt_status batch_prepare(ntt_batch* b, const ntt_batch_item* items, size_t count
     const ntt_plan* p = nullptr;
     ntt_status st = cached_plan(it.N, it.q, &p);
     if (st) return st;
-    BatchTask& t = b->host[k];
+    BatchTask& t = staged_tasks(b)[k];
     t.out = it.out;
     t.in = it.in;
     t.in2 = it.in2;
@@ -199,7 +210,7 @@ ntt_status batch_prepare(ntt_batch* b, const ntt_batch_item* items, size_t count
     t.logN = (uint32_t)p->logN;
     t.op = it.op;
   }
-  *reinterpret_cast<uint32_t*>(b->host + b->capacity) = (uint32_t)count;
+  *reinterpret_cast<uint32_t*>(b->host) = (uint32_t)count;
   *out_count = count;
   return NTT_OK;
 }
@@ -215,14 +226,70 @@ int batch_grid(const ntt_batch* b, size_t count) {
   return g < 1 ? 1 : g;
 }
 
-// Enqueues [descriptor copy, counter reset, persistent kernel] on `stream`.
-ntt_status batch_enqueue(ntt_batch* b, int grid, hipStream_t stream) {
-  const size_t bytes = b->capacity * sizeof(BatchTask) + sizeof(uint32_t);
-  if (hipMemcpyAsync(b->dev, b->host, bytes, hipMemcpyHostToDevice, stream) != hipSuccess) return NTT_EDEVICE;
-  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, stream, b->dev_counter);
-  hipLaunchKernelGGL(ntt_batch_kernel, dim3(grid), dim3(kBatchThreads), 0, stream, b->dev, b->dev_count,
-                     b->dev_counter);
+// Enqueues [descriptor copy of `staged` tasks, counter reset, persistent kernel] on `stream`.
+ntt_status batch_enqueue(ntt_batch* b, size_t staged, int grid, hipStream_t stream) {
+  if (hipMemcpyAsync(b->dev + kDevHead, b->host, stage_bytes(staged), hipMemcpyHostToDevice, stream) != hipSuccess)
+    return NTT_EDEVICE;
+  u32* counter = reinterpret_cast<u32*>(b->dev);
+  const u32* count = reinterpret_cast<const u32*>(b->dev + kDevHead);
+  const BatchTask* tasks = reinterpret_cast<const BatchTask*>(b->dev + kDevHead + kStageHead);
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, stream, counter);
+  hipLaunchKernelGGL(ntt_batch_kernel, dim3(grid), dim3(kBatchThreads), 0, stream, tasks, count, counter);
   return hipGetLastError() == hipSuccess ? NTT_OK : NTT_EDEVICE;
+}
+
+static ntt_status batch_launch_staged(ntt_batch* b, size_t n, hipStream_t s, bool graph) {
+  ntt_status st = NTT_OK;
+  if (!graph) {
+    st = batch_enqueue(b, n, batch_grid(b, n), s);
+    if (st) return st;
+  } else {
+    if (!b->graph_exec) {
+      // captured once with the full-capacity copy and grid; the kernel reads the count from device memory
+      const int grid = batch_grid(b, b->capacity);
+      hipStream_t cap = nullptr;
+      if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return NTT_EDEVICE;
+      if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        return NTT_EDEVICE;
+      }
+      st = batch_enqueue(b, b->capacity, grid, cap);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(cap, &g);
+      (void)hipStreamDestroy(cap);
+      if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (e != hipSuccess || !g) return NTT_EDEVICE;
+      if (hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return NTT_EDEVICE;
+      }
+      b->graph = g;
+    }
+    if (hipGraphLaunch(b->graph_exec, s) != hipSuccess) return NTT_EDEVICE;
+  }
+  if (hipEventRecord(b->done, s) != hipSuccess) return NTT_EDEVICE;
+  b->pending = true;
+  return NTT_OK;
+}
+
+ntt_status batch_launch_tasks(ntt_batch* b, const BatchTask* tasks, size_t count, hipStream_t stream, bool graph) {
+  if (count == 0) return NTT_OK;
+  if (count > b->capacity) return NTT_EINVAL_COUNT;
+  ntt_status st = wait_staging(b);
+  if (st) return st;
+  std::vector<std::pair<uint64_t, size_t>> order(count);
+  for (size_t i = 0; i < count; ++i) order[i] = {task_cost(tasks[i].logN, tasks[i].op), i};
+  std::stable_sort(order.begin(), order.end(),
+                   [](const std::pair<uint64_t, size_t>& a, const std::pair<uint64_t, size_t>& c) {
+                     return a.first > c.first;
+                   });
+  BatchTask* dst = staged_tasks(b);
+  for (size_t k = 0; k < count; ++k) dst[k] = tasks[order[k].second];
+  *reinterpret_cast<uint32_t*>(b->host) = (uint32_t)count;
+  return batch_launch_staged(b, count, stream, graph);
 }
 
 }  // namespace nttamd
@@ -238,16 +305,14 @@ ntt_status ntt_batch_create(ntt_batch** out, size_t capacity) {
   ntt_batch* b = new (std::nothrow) ntt_batch();
   if (!b) return NTT_ENOMEM;
   b->capacity = capacity;
-  const size_t bytes = capacity * sizeof(BatchTask) + sizeof(uint32_t);
+  const size_t bytes = stage_bytes(capacity);
   if (hipGetDevice(&b->device) != hipSuccess) { delete b; return NTT_EDEVICE; }
   if (hipHostMalloc((void**)&b->host, bytes, hipHostMallocDefault) != hipSuccess) { delete b; return NTT_ENOMEM; }
-  if (hipMalloc((void**)&b->dev, bytes + 256) != hipSuccess) {
+  if (hipMalloc((void**)&b->dev, kDevHead + bytes) != hipSuccess) {
     (void)hipHostFree(b->host);
     delete b;
     return NTT_ENOMEM;
   }
-  b->dev_count = reinterpret_cast<uint32_t*>(b->dev + capacity);
-  b->dev_counter = b->dev_count + 32;                     // separate 128-byte line
   if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
     (void)hipFree(b->dev);
     (void)hipHostFree(b->host);
@@ -290,11 +355,7 @@ ntt_status ntt_batch_run(ntt_batch* b, const ntt_batch_item* items, size_t count
   size_t n = 0;
   ntt_status st = batch_prepare(b, items, count, &n);
   if (st) return st;
-  st = batch_enqueue(b, batch_grid(b, n), (hipStream_t)stream);
-  if (st) return st;
-  if (hipEventRecord(b->done, (hipStream_t)stream) != hipSuccess) return NTT_EDEVICE;
-  b->pending = true;
-  return NTT_OK;
+  return batch_launch_staged(b, n, (hipStream_t)stream, false);
 }
 
 ntt_status ntt_batch_run_graph(ntt_batch* b, const ntt_batch_item* items, size_t count, ntt_stream_t stream) {
@@ -304,35 +365,7 @@ ntt_status ntt_batch_run_graph(ntt_batch* b, const ntt_batch_item* items, size_t
   size_t n = 0;
   ntt_status st = batch_prepare(b, items, count, &n);
   if (st) return st;
-  hipStream_t s = (hipStream_t)stream;
-  if (!b->graph_exec) {
-    // capture once with the full-capacity grid; the kernel reads the count from device memory
-    const int grid = batch_grid(b, b->capacity);
-    hipStream_t cap = nullptr;
-    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return NTT_EDEVICE;
-    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-      (void)hipStreamDestroy(cap);
-      return NTT_EDEVICE;
-    }
-    st = batch_enqueue(b, grid, cap);
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(cap, &g);
-    (void)hipStreamDestroy(cap);
-    if (st) {
-      if (g) (void)hipGraphDestroy(g);
-      return st;
-    }
-    if (e != hipSuccess || !g) return NTT_EDEVICE;
-    if (hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
-      (void)hipGraphDestroy(g);
-      return NTT_EDEVICE;
-    }
-    b->graph = g;
-  }
-  if (hipGraphLaunch(b->graph_exec, s) != hipSuccess) return NTT_EDEVICE;
-  if (hipEventRecord(b->done, s) != hipSuccess) return NTT_EDEVICE;
-  b->pending = true;
-  return NTT_OK;
+  return batch_launch_staged(b, n, (hipStream_t)stream, true);
 }
 
 ntt_status ntt_batch_autotune(ntt_batch* b, const ntt_batch_item* items, size_t count, ntt_stream_t stream,

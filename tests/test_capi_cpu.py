@@ -26,7 +26,8 @@ def nt():
 def test_header_declares_the_boundary():
     names = _declared_functions()
     for required in ["ntt_forward", "ntt_inverse", "eltwise_mult_mod", "eltwise_add_mod", "ntt_plan_create",
-                     "ntt_forward_rns", "poly_mul_rns"]:
+                     "ntt_forward_rns", "poly_mul_rns", "ntt_batch_run", "ntt_server_create", "ntt_server_submit",
+                     "ntt_server_poll", "ntt_server_destroy"]:
         assert required in names
 
 
@@ -37,7 +38,7 @@ def test_library_exports_every_declared_symbol(nt):
 
 
 def test_status_strings(nt):
-    for code in range(0, -12, -1):
+    for code in range(0, -13, -1):
         s = nt.status_string(code)
         assert s and s != "unknown status"
     assert nt.status_string(-999) == "unknown status"
@@ -83,3 +84,20 @@ def test_argument_validation_without_device(nt):
     assert L.poly_mul_rns(fake, other, fake, 1024, mod, 1, 1, None, None) == nt.NTT_EALIAS
     assert L.ntt_plan_destroy(None) == nt.NTT_EINVAL_POINTER
     assert L.ntt_plan_root(None) == 0
+
+
+def test_server_config_validation_without_device(nt):
+    """Invalid server configurations are refused before any device call."""
+    lib = _raw(nt)
+    h = ctypes.c_void_p()
+    assert lib.ntt_server_create(None, None) == -5
+    for kw in ({"mode": 3}, {"streams": 5}, {"max_batch_tasks": 10}, {"max_batch_tasks": (1 << 20) + 1}):
+        cfg = nt.ServerConfig(**kw)
+        assert lib.ntt_server_create(ctypes.byref(h), ctypes.byref(cfg)) == -7, kw
+        assert not h.value
+    assert lib.ntt_server_submit(None, None, None) == -5
+    assert lib.ntt_server_poll(None, 1, None) == -5
+    assert lib.ntt_server_drain(None, 0) == -5
+    assert lib.ntt_server_release(None, 1) == -5
+    assert lib.ntt_server_destroy(None) == -5
+    assert lib.ntt_server_now_ns() > 0
