@@ -169,6 +169,93 @@ def time_uneven_batch(nt, torch, primes, reps=10):
     return res
 
 
+SERVE_RATES = (1000, 2000, 5000, 10000, 20000, 50000)
+
+
+class OperandPool:
+    """Resident operands for the serving stream: for every N in 2^12..2^17, `per_n` pairs of
+    [40][N] arrays whose limb l is uniform in [0, q_l) for the l-th prime of the 40-prime serving
+    pool; a request with L limbs reads the first L*N words (contiguous [L][N])."""
+
+    def __init__(self, torch, moduli, per_n=2):
+        from synthetic import uniform_mod, unit_seed
+        self.bufs = {}
+        dev = torch.device("cuda:0")
+        for logN in range(12, 18):
+            N = 1 << logN
+            for p in range(per_n):
+                for op in range(2):
+                    h = np.empty(len(moduli) * N, dtype=np.uint64)
+                    for l, q in enumerate(moduli):
+                        h[l * N:(l + 1) * N] = uniform_mod(unit_seed(6, logN, p, op, l), N, q)
+                    self.bufs[(logN, p, op)] = torch.from_numpy(h.view(np.int64)).to(dev)
+        self.per_n = per_n
+
+    def pick(self, logN, k):
+        p = k % self.per_n
+        return self.bufs[(logN, p, 0)], self.bufs[(logN, p, 1)]
+
+
+def serve_schedule(rate, n):
+    """n requests of a Poisson stream at `rate` req/s: N uniform in {2^12..2^17}, L uniform in [1, 40]."""
+    from synthetic import exponential, uniform_int, unit_seed
+    gaps = exponential(unit_seed(7, rate, 0), n, 1e9 / rate)
+    offs = np.cumsum(gaps).astype(np.int64)
+    logNs = uniform_int(unit_seed(7, rate, 1), n, 12, 17)
+    Ls = uniform_int(unit_seed(7, rate, 2), n, 1, 40)
+    return offs, logNs, Ls
+
+
+def run_served(nt, pool, moduli, mode, rate, n, streams=2):
+    """One open-loop run; latency = completion seen by the scheduler - scheduled arrival."""
+    offs, logNs, Ls = serve_schedule(rate, n)
+    srv = nt.Server(mode=mode, streams=streams, release_on_completion=True)
+    for logN in range(12, 18):                   # warm-up: plans of every (N, q) and the kernels
+        a, b = pool.pick(logN, 0)
+        srv.submit(a, b, 1 << logN, moduli)
+    srv.drain(timeout_s=60)
+    t0 = nt.now_ns() + 30_000_000 + n * 40_000   # every request is handed over before the first arrival
+    tickets = [srv.submit(*pool.pick(int(logNs[k]), k), 1 << int(logNs[k]), moduli[:int(Ls[k])],
+                          arrival_ns=t0 + int(offs[k])) for k in range(n)]
+    late = nt.now_ns() - t0
+    srv.drain(timeout_s=600)
+    infos = srv.query(tickets)
+    st = srv.stats()
+    srv.close()
+    lat = np.array([i.done_ns - i.arrival_ns for i in infos], dtype=np.float64) / 1e6
+    end = max(i.done_ns for i in infos)
+    ok = all(i.state == nt.REQ_DONE for i in infos)
+    return {"rate": rate, "requests": n, "ok": ok, "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3), "mean_ms": round(float(lat.mean()), 3),
+            "throughput_rps": round(n / ((end - t0) / 1e9), 1),
+            "limb_products_per_s": round(float(Ls.sum()) / ((end - t0) / 1e9), 1),
+            "launches": st["launches"], "tasks_per_launch": round(st["tasks"] / max(1, st["launches"]), 1),
+            "submit_margin_ms": round(-late / 1e6, 1)}
+
+
+def time_serving(nt, torch, primes, rates=SERVE_RATES, max_requests=4000, seconds=1.0,
+                 modes=("batched", "fifo", "fifo_per_limb")):
+    moduli = primes["serving"]["moduli"]
+    pool = OperandPool(torch, moduli)
+    code = {"batched": nt.SERVE_BATCHED, "fifo": nt.SERVE_FIFO, "fifo_per_limb": nt.SERVE_FIFO_PER_LIMB}
+    res = {"workload": "Poisson stream of negacyclic products, N ~ U{2^12..2^17}, L ~ U[1,40] "
+                       "(50-60-bit primes), operands resident",
+           "requests_per_rate": "min(%d, rate x %.1f s)" % (max_requests, seconds)}
+    for m in modes:
+        runs = []
+        for r in rates:
+            n = int(min(max_requests, r * seconds))
+            runs.append(run_served(nt, pool, moduli, code[m], r, n))
+            print("serve %s rate %d: p50 %.2f ms p99 %.2f ms, %.0f req/s" %
+                  (m, r, runs[-1]["p50_ms"], runs[-1]["p99_ms"], runs[-1]["throughput_rps"]), file=sys.stderr,
+                  flush=True)
+        ok10 = [x["rate"] for x in runs if x["p99_ms"] <= 10.0 and x["throughput_rps"] >= 0.9 * x["rate"]]
+        res[m] = {"runs": runs, "max_rate_p99_le_10ms": max(ok10) if ok10 else None}
+    del pool
+    torch.cuda.empty_cache()
+    return res
+
+
 def time_single_1024(nt, torch, primes, reps=200):
     """Per-call latency of one forward and one inverse NTT at N = 1024 (single limb)."""
     p1 = primes["single_1024"]
@@ -203,6 +290,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving sweep (full size)")
+    ap.add_argument("--serve-requests", type=int, default=4000, help="cap on requests per arrival rate")
+    ap.add_argument("--serve-seconds", type=float, default=1.0, help="arrival window per rate")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; the path shards over GPUs by limbs "
@@ -212,6 +303,11 @@ def main():
 
     import torch
     import paper_2103_16400_amd as nt
+
+    if args.serve_only:
+        print(json.dumps({"serving": time_serving(nt, torch, load_primes(), max_requests=args.serve_requests,
+                                                  seconds=args.serve_seconds)}), flush=True)
+        return
 
     primes = load_primes()["rns_16384"]
     N, moduli, psis = primes["N"], primes["moduli"], primes["psi"]
@@ -287,6 +383,9 @@ def main():
         out["large_ring_n65536_l32"] = time_large_ring(nt, torch, load_primes())
         out["single_n1024"] = time_single_1024(nt, torch, load_primes())
         out["uneven_batch_256polys"] = time_uneven_batch(nt, torch, load_primes())
+        if not args.no_serve:
+            out["serving"] = time_serving(nt, torch, load_primes(), max_requests=args.serve_requests,
+                                          seconds=args.serve_seconds)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, moduli, psis, args.cpu_seconds)
     print(json.dumps(out), flush=True)
