@@ -32,6 +32,29 @@ import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes of the dominant kernel (forward transform, N = 2^14, 4096 limbs, one launch) from two
+# rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean of
+# 3 dispatches), each scaled by the same counter's reading for a plain 1 GiB device copy (FETCH_SIZE
+# read 524300 KiB for 1048576 KiB copied: x2.0; WRITE_SIZE read 1048576 KiB: x1.0).  Valid only for
+# the kernel sources they were taken with, identified by the SHA-256 of these files.
+TRAFFIC_FWD_N16384 = {
+    "fetch_kib": 275576.5, "fetch_scale": 2.0, "write_kib": 524288.0, "write_scale": 1.0,
+    "sources": ["ntt_onchip.hip", "ntt_onchip.h", "ntt_common.h", "modarith.h"],
+    "sha256": "0d81557cc8ca152cced2836837c7cb76d7cba4deeb87ea4524a1bf38e06ca057",
+}
+
+
+def measured_traffic(t):
+    """HBM bytes per launch from the stored counters, or None once the kernel sources changed."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in t["sources"]:
+        with open(os.path.join(ROOT, "paper_2103_16400_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != t["sha256"]:
+        return None
+    return int((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024)
+
 
 def load_primes():
     with open(os.path.join(ROOT, "tests", "golden", "primes.json")) as f:
@@ -294,6 +317,8 @@ def main():
     ap.add_argument("--serve-only", action="store_true", help="run only the serving sweep (full size)")
     ap.add_argument("--serve-requests", type=int, default=4000, help="cap on requests per arrival rate")
     ap.add_argument("--serve-seconds", type=float, default=1.0, help="arrival window per rate")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 4 times (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; the path shards over GPUs by limbs "
@@ -303,6 +328,15 @@ def main():
 
     import torch
     import paper_2103_16400_amd as nt
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.int64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_dispatch": src.numel() * 8}), flush=True)
+        return
 
     if args.serve_only:
         print(json.dumps({"serving": time_serving(nt, torch, load_primes(), max_requests=args.serve_requests,
@@ -371,7 +405,8 @@ def main():
                    "step": "fwd(a) 1->4; fwd(b) 1->4 fused with modmul f=4; inv 1->1 fused with acc add",
                    "forward_ntts_per_step": fwd_per_step},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(TRAFFIC_FWD_N16384) if (N, limbs) == (16384, 4096) else None,
                      "kernel": "ntt_onchip_kernel<fwd, N=2^14>: forward NTT of %d limbs, one launch" % limbs,
                      "avg_ms": round(fwd_ms, 4), "alg_bytes": alg_bytes},
         "fwd_ntt_rate": round(limbs / (fwd_ms * 1e-3), 1),

@@ -229,9 +229,12 @@ ntt_status poly_mul_acc_rns(uint64_t* acc, const uint64_t* a, const uint64_t* b,
  *   pinned and device descriptor buffers; not thread-safe: one context per
  *   host thread or external locking).
  * ntt_batch_run: copies the descriptors and launches, asynchronously on
- *   `stream` (waits first for the context's previous run to release its
- *   staging buffer).  Errors: NTT_EINVAL_* for a bad task (nothing launched).
- * ntt_batch_run_graph: same work through a hipGraph captured on first use:
+ *   `stream`.  The context holds two staging sets used in turn, so the host
+ *   prepares a run while the previous one executes; a run first waits for
+ *   the run two before it.  Errors: NTT_EINVAL_* for a bad task (nothing
+ *   launched).
+ * ntt_batch_run_graph: same work through a hipGraph (one per staging set)
+ *   captured on first use:
  *   [descriptor copy, counter reset, persistent kernel]; the graph reads the
  *   task list and count from device memory, so it is replayed unchanged for
  *   every later batch of up to `capacity` tasks.

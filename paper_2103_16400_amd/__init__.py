@@ -19,6 +19,10 @@ if not os.path.exists(LIB_PATH):
         "libntt_hip.so is not built (expected at %s); run `python paper_2103_16400_amd/build.py` "
         "or __graft_entry__.build()" % LIB_PATH)
 
+# torch ships its own HIP runtime (same soname as ROCm's); loading it first makes
+# this library bind to that one runtime instead of bringing in a second copy.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 _U64 = ctypes.c_uint64

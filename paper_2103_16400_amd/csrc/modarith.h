@@ -55,32 +55,202 @@ __device__ __forceinline__ u64 shoup_mul(u64 x, u64 w, u64 wp, u64 nq) {
 // x - m if x >= m, else x (one conditional subtraction).
 __device__ __forceinline__ u64 csub(u64 x, u64 m) { return x >= m ? x - m : x; }
 
-// Algorithm 4 (Harvey forward butterfly), beta = 2^64, inputs in [0, 4q),
-// outputs in [0, 4q):  X0 <- X0 + W X1,  X1 <- X0 - W X1  (mod q).
-__device__ __forceinline__ void harvey_fwd(u64& x0, u64& x1, u64 w, u64 wp, u64 q2, u64 nq) {
+// ---- Harvey butterflies, plain C++ -----------------------------------------
+// Algorithm 4 (forward, inputs and outputs in [0, 4q)) and Algorithm 5
+// (inverse, [0, 2q)), written directly; the hand-scheduled versions below
+// compute the same words.
+__device__ __forceinline__ void harvey_fwd_c(u64& x0, u64& x1, u64 w, u64 wp, u64 q2, u64 nq) {
   const u64 a = csub(x0, q2);
   const u64 t = shoup_mul(x1, w, wp, nq);          // [0, 2q)
   x0 = a + t;
   x1 = a + q2 - t;
 }
-
-// Algorithm 5 (Harvey inverse butterfly), inputs in [0, 2q), outputs in
-// [0, 2q):  X0 <- X0 + X1,  X1 <- W (X0 - X1)  (mod q).
-__device__ __forceinline__ void harvey_inv(u64& x0, u64& x1, u64 w, u64 wp, u64 q2, u64 nq) {
+__device__ __forceinline__ void harvey_inv_c(u64& x0, u64& x1, u64 w, u64 wp, u64 q2, u64 nq) {
   const u64 y0 = csub(x0 + x1, q2);
   const u64 t = x0 + q2 - x1;
   x1 = shoup_mul(t, w, wp, nq);
   x0 = y0;
 }
+__device__ __forceinline__ void harvey_inv_last_c(u64& x0, u64& x1, u64 ni, u64 nip, u64 wn, u64 wnp, u64 q2,
+                                                  u64 nq) {
+  const u64 s = x0 + x1;
+  const u64 t = x0 + q2 - x1;
+  x0 = shoup_mul(s, ni, nip, nq);
+  x1 = shoup_mul(t, wn, wnp, nq);
+}
+
+// ---- Harvey butterflies in gfx950 assembly --------------------------------
+// The arithmetic of Algorithms 4 and 5 exactly as in shoup_mul / csub above
+// (exact MulHi, low-word remainder, the same lazy corrections), scheduled by
+// hand as one statement per butterfly.  Written in C++, every 32-bit value
+// that enters a 64-bit addend ({x, 0}) costs the compiler a register copy and
+// its carries cost hazard padding; here
+//   - x0 and x1 are updated in place (tied operands) and every temporary
+//     lives in six fixed scratch registers, the pairs P = v[122:123],
+//     T = v[124:125], M = v[126:127], so a butterfly adds little register
+//     pressure and halves of temporaries can be named;
+//   - the MulHi is four 32 x 32 -> 64 products; the carry of its middle sum
+//     travels in an SGPR pair;
+//   - the remainder T = W X + Q nq (mod 2^64) is two products into the pair
+//     plus four cross products that only reach the high word, summed in the
+//     low word of M and shifted up;
+//   - each VALU write of an SGPR (carry, compare mask, borrow) is followed by
+//     at least two other instructions before a VALU reads it;
+//   - every input is read before the tied output that may share its register
+//     is written.
+// Kernels that use these butterflies need a VGPR budget of at least 128.
+#define NTTAMD_CLOBBERS "v122", "v123", "v124", "v125", "v126", "v127"
+
+// Algorithm 4 (Harvey forward butterfly), beta = 2^64, inputs in [0, 4q),
+// outputs in [0, 4q):  X0 <- X0 + W X1,  X1 <- X0 - W X1  (mod q).
+// nq = 2^64 - q, nq2 = 2^64 - 2q.  Only P = v[124:125] and T = v[126:127]
+// are used: once Q has served its low-word product, its pair holds the 32-bit
+// cross products.  The outputs are written only after every operand has been
+// read, so they may reuse the input registers.
+__device__ __forceinline__ void harvey_fwd(u64& x0, u64& x1, u64 w, u64 wp, u64 q2, u64 nq, u64 nq2) {
+  u64 k, c, j, b, y0, y1;
+  asm volatile("v_cmp_le_u64 %[k], %[q2], %[x0]\n\t"                 // x0 >= 2q
+      "v_mad_u64_u32 v[124:125], %[j], %[pl], %[x1l], 0\n\t"        // P = MulHi(W', X1) ...
+      "v_lshrrev_b64 v[124:125], 32, v[124:125]\n\t"
+      "v_mad_u64_u32 v[124:125], %[j], %[pl], %[x1h], v[124:125]\n\t"
+      "v_mad_u64_u32 v[124:125], %[c], %[ph], %[x1l], v[124:125]\n\t"
+      "v_mov_b32 v124, v125\n\t"
+      "v_mad_u64_u32 v[126:127], %[j], %[wl], %[x1l], 0\n\t"        // T = W X1 (low products)
+      "v_addc_co_u32 v125, %[j], 0, 0, %[c]\n\t"
+      "v_mad_u64_u32 v[124:125], %[j], %[ph], %[x1h], v[124:125]\n\t"   // ... P = Q
+      "v_mad_u64_u32 v[126:127], %[j], v124, %[nql], v[126:127]\n\t"    // T += Q0 nq0
+      "v_mul_lo_u32 v124, v124, %[nqh]\n\t"                         // cross products (high word only)
+      "v_mul_lo_u32 v125, v125, %[nql]\n\t"
+      "v_add3_u32 v127, v127, v124, v125\n\t"
+      "v_mul_lo_u32 v124, %[wl], %[x1h]\n\t"
+      "v_mul_lo_u32 v125, %[wh], %[x1l]\n\t"
+      "v_add3_u32 v127, v127, v124, v125\n\t"                       // T = W X1 mod q in [0, 2q)
+      "v_lshl_add_u64 v[124:125], %[x0], 0, %[nq2]\n\t"            // x0 - 2q
+      "v_cndmask_b32 v124, %[x0l], v124, %[k]\n\t"
+      "v_cndmask_b32 v125, %[x0h], v125, %[k]\n\t"                  // A = x0 mod 2q in [0, 2q)
+      "v_lshl_add_u64 %[y0], v[124:125], 0, v[126:127]\n\t"         // X0 = A + T
+      "v_lshl_add_u64 v[124:125], v[124:125], 0, %[q2]\n\t"         // A + 2q
+      "v_sub_co_u32 v124, %[b], v124, v126\n\t"
+      "s_nop 1\n\t"
+      "v_subb_co_u32 v125, %[b], v125, v127, %[b]\n\t"
+      "v_lshl_add_u64 %[y1], v[124:125], 0, 0"                       // X1 = A + 2q - T
+      : [y0] "=v"(y0), [y1] "=v"(y1), [k] "=&s"(k), [c] "=&s"(c), [j] "=&s"(j), [b] "=&s"(b)
+      : [x0] "v"(x0), [x0l] "v"(lo32(x0)), [x0h] "v"(hi32(x0)), [x1l] "v"(lo32(x1)), [x1h] "v"(hi32(x1)),
+        [wl] "v"(lo32(w)), [wh] "v"(hi32(w)), [pl] "v"(lo32(wp)), [ph] "v"(hi32(wp)), [q2] "s"(q2), [nq2] "s"(nq2),
+        [nql] "s"(lo32(nq)), [nqh] "s"(hi32(nq))
+      : "v124", "v125", "v126", "v127");
+  x0 = y0;
+  x1 = y1;
+}
+
+// Algorithm 5 (Harvey inverse butterfly), inputs in [0, 2q), outputs in
+// [0, 2q):  X0 <- X0 + X1,  X1 <- W (X0 - X1)  (mod q).  X0 is updated in
+// place; X1 is written last, so it may reuse the input registers.
+__device__ __forceinline__ void harvey_inv(u64& x0, u64& x1, u64 w, u64 wp, u64 q2, u64 nq, u64 nq2) {
+  u64 k, c, j, b, y1;
+  asm volatile("v_lshl_add_u64 v[124:125], %[x0], 0, %[q2]\n\t"              // x0 + 2q
+      "v_lshl_add_u64 v[126:127], %[x0], 0, %[x1]\n\t"              // S = x0 + x1 < 4q
+      "v_sub_co_u32 v124, %[b], v124, %[x1l]\n\t"
+      "v_cmp_le_u64 %[k], %[q2], v[126:127]\n\t"                    // S >= 2q
+      "v_lshl_add_u64 v[122:123], v[126:127], 0, %[nq2]\n\t"        // S - 2q
+      "v_subb_co_u32 v125, %[b], v125, %[x1h], %[b]\n\t"            // T = D = x0 + 2q - x1 < 4q
+      "v_cndmask_b32 v126, v126, v122, %[k]\n\t"
+      "v_cndmask_b32 v127, v127, v123, %[k]\n\t"                    // M = S mod 2q
+      "v_mad_u64_u32 v[122:123], %[j], %[pl], v124, 0\n\t"          // P = MulHi(W', D) ...
+      "v_lshl_add_u64 %[x0], v[126:127], 0, 0\n\t"                  // X0 = S mod 2q
+      "v_lshrrev_b64 v[122:123], 32, v[122:123]\n\t"
+      "v_mad_u64_u32 v[122:123], %[j], %[pl], v125, v[122:123]\n\t"
+      "v_mad_u64_u32 v[122:123], %[c], %[ph], v124, v[122:123]\n\t"
+      "v_mov_b32 v122, v123\n\t"
+      "v_mad_u64_u32 v[126:127], %[j], %[wh], v124, 0\n\t"          // M = cross products
+      "v_addc_co_u32 v123, %[j], 0, 0, %[c]\n\t"
+      "v_mad_u64_u32 v[122:123], %[j], %[ph], v125, v[122:123]\n\t" // ... P = Q
+      "v_mad_u64_u32 v[126:127], %[j], %[wl], v125, v[126:127]\n\t"
+      "v_mad_u64_u32 v[124:125], %[j], %[wl], v124, 0\n\t"          // T = W D (low products); D dies
+      "v_mad_u64_u32 v[124:125], %[j], v122, %[nql], v[124:125]\n\t"
+      "v_mad_u64_u32 v[126:127], %[j], v122, %[nqh], v[126:127]\n\t"
+      "v_mad_u64_u32 v[126:127], %[j], v123, %[nql], v[126:127]\n\t"
+      "v_lshlrev_b64 v[126:127], 32, v[126:127]\n\t"
+      "v_lshl_add_u64 v[124:125], v[124:125], 0, v[126:127]\n\t"
+      "v_lshl_add_u64 %[y1], v[124:125], 0, 0"                       // X1 = W D mod q in [0, 2q)
+      : [x0] "+v"(x0), [y1] "=v"(y1), [k] "=&s"(k), [c] "=&s"(c), [j] "=&s"(j), [b] "=&s"(b)
+      : [x1] "v"(x1), [x1l] "v"(lo32(x1)), [x1h] "v"(hi32(x1)), [wl] "v"(lo32(w)), [wh] "v"(hi32(w)),
+        [pl] "v"(lo32(wp)), [ph] "v"(hi32(wp)), [q2] "s"(q2), [nq2] "s"(nq2), [nql] "s"(lo32(nq)),
+        [nqh] "s"(hi32(nq))
+      : NTTAMD_CLOBBERS);
+  x1 = y1;
+}
 
 // Last inverse stage fused with the scaling by N^{-1} (Algorithm 3's final
 // loop): X0 <- N^{-1} (X0 + X1), X1 <- (W N^{-1}) (X0 - X1), both in [0, 2q).
+// X1 is first copied into M so that both outputs, updated in place, can
+// serve as scratch pairs once S and D are formed.  The four constants are
+// uniform and enter as SGPRs (each instruction reads at most one SGPR).
 __device__ __forceinline__ void harvey_inv_last(u64& x0, u64& x1, u64 ni, u64 nip, u64 wn, u64 wnp,
                                                 u64 q2, u64 nq) {
-  const u64 s = x0 + x1;                           // < 4q < 2^64
-  const u64 t = x0 + q2 - x1;                      // < 4q
-  x0 = shoup_mul(s, ni, nip, nq);
-  x1 = shoup_mul(t, wn, wnp, nq);
+  u64 c, j, b;
+  asm volatile("v_lshl_add_u64 v[126:127], %[x1], 0, 0\n\t"                  // M = x1
+      "v_lshl_add_u64 v[124:125], %[x0], 0, %[q2]\n\t"              // x0 + 2q
+      "v_lshl_add_u64 v[122:123], %[x0], 0, %[x1]\n\t"              // P = S = x0 + x1 < 4q
+      "v_sub_co_u32 v124, %[b], v124, v126\n\t"
+      "v_mad_u64_u32 %[x0], %[j], %[nil], v122, 0\n\t"              // X0 = N^-1 S (low products) ...
+      "v_mad_u64_u32 %[x1], %[j], %[nih], v122, 0\n\t"              // X1 = its cross products
+      "v_subb_co_u32 v125, %[b], v125, v127, %[b]\n\t"              // T = D = x0 + 2q - x1 < 4q
+      "v_mad_u64_u32 %[x1], %[j], %[nil], v123, %[x1]\n\t"
+      "v_mad_u64_u32 v[126:127], %[j], %[npl], v122, 0\n\t"         // M = MulHi(N^-1', S) ...
+      "v_lshrrev_b64 v[126:127], 32, v[126:127]\n\t"
+      "v_mad_u64_u32 v[126:127], %[j], %[npl], v123, v[126:127]\n\t"
+      "v_mad_u64_u32 v[126:127], %[c], %[nph], v122, v[126:127]\n\t"
+      "v_mov_b32 v126, v127\n\t"
+      "s_nop 0\n\t"
+      "v_addc_co_u32 v127, %[j], 0, 0, %[c]\n\t"
+      "v_mad_u64_u32 v[126:127], %[j], %[nph], v123, v[126:127]\n\t" // ... M = Q
+      "v_mad_u64_u32 %[x0], %[j], v126, %[nql], %[x0]\n\t"
+      "v_mad_u64_u32 %[x1], %[j], v126, %[nqh], %[x1]\n\t"
+      "v_mad_u64_u32 %[x1], %[j], v127, %[nql], %[x1]\n\t"
+      "v_lshlrev_b64 %[x1], 32, %[x1]\n\t"
+      "v_lshl_add_u64 %[x0], %[x0], 0, %[x1]\n\t"                   // X0 = N^-1 S mod q in [0, 2q)
+      "v_mad_u64_u32 v[122:123], %[j], %[wpl], v124, 0\n\t"         // P = MulHi((W N^-1)', D) ...
+      "v_lshrrev_b64 v[122:123], 32, v[122:123]\n\t"
+      "v_mad_u64_u32 v[122:123], %[j], %[wpl], v125, v[122:123]\n\t"
+      "v_mad_u64_u32 v[122:123], %[c], %[wph], v124, v[122:123]\n\t"
+      "v_mov_b32 v122, v123\n\t"
+      "v_mad_u64_u32 %[x1], %[j], %[wnl], v124, 0\n\t"              // X1 = W N^-1 D (low products)
+      "v_addc_co_u32 v123, %[j], 0, 0, %[c]\n\t"
+      "v_mad_u64_u32 v[122:123], %[j], %[wph], v125, v[122:123]\n\t" // ... P = Q
+      "v_mad_u64_u32 v[126:127], %[j], %[wnh], v124, 0\n\t"         // M = cross products
+      "v_mad_u64_u32 v[126:127], %[j], %[wnl], v125, v[126:127]\n\t"
+      "v_mad_u64_u32 %[x1], %[j], v122, %[nql], %[x1]\n\t"
+      "v_mad_u64_u32 v[126:127], %[j], v122, %[nqh], v[126:127]\n\t"
+      "v_mad_u64_u32 v[126:127], %[j], v123, %[nql], v[126:127]\n\t"
+      "v_lshlrev_b64 v[126:127], 32, v[126:127]\n\t"
+      "v_lshl_add_u64 %[x1], %[x1], 0, v[126:127]"                   // X1 = W N^-1 D mod q in [0, 2q)
+      : [x0] "+v"(x0), [x1] "+v"(x1), [c] "=&s"(c), [j] "=&s"(j), [b] "=&s"(b)
+      : [nil] "s"(lo32(ni)), [nih] "s"(hi32(ni)), [npl] "s"(lo32(nip)), [nph] "s"(hi32(nip)), [wnl] "s"(lo32(wn)),
+        [wnh] "s"(hi32(wn)), [wpl] "s"(lo32(wnp)), [wph] "s"(hi32(wnp)), [q2] "s"(q2), [nql] "s"(lo32(nq)),
+        [nqh] "s"(hi32(nq))
+      : NTTAMD_CLOBBERS);
+}
+
+#undef NTTAMD_CLOBBERS
+
+// Butterfly selection for the transform templates: HAND = the hand-scheduled
+// versions above, else the plain C++ ones (used where the statements would sit
+// inside non-inlined device functions).
+template <bool HAND>
+__device__ __forceinline__ void bfly_fwd(u64& x0, u64& x1, u64 w, u64 wp, u64 q2, u64 nq, u64 nq2) {
+  if constexpr (HAND) harvey_fwd(x0, x1, w, wp, q2, nq, nq2);
+  else harvey_fwd_c(x0, x1, w, wp, q2, nq);
+}
+template <bool HAND>
+__device__ __forceinline__ void bfly_inv(u64& x0, u64& x1, u64 w, u64 wp, u64 q2, u64 nq, u64 nq2) {
+  if constexpr (HAND) harvey_inv(x0, x1, w, wp, q2, nq, nq2);
+  else harvey_inv_c(x0, x1, w, wp, q2, nq);
+}
+template <bool HAND>
+__device__ __forceinline__ void bfly_inv_last(u64& x0, u64& x1, u64 ni, u64 nip, u64 wn, u64 wnp, u64 q2, u64 nq) {
+  if constexpr (HAND) harvey_inv_last(x0, x1, ni, nip, wn, wnp, q2, nq);
+  else harvey_inv_last_c(x0, x1, ni, nip, wn, wnp, q2, nq);
 }
 
 // x mod q for x in [0, 4q): the two-step small_mod of Section 4.

@@ -10,6 +10,9 @@
 //   * N >= 2^15: both passes of the two-pass transform (ntt_tile.h), one
 //     4096-coefficient tile at a time; the intermediate stays in the limb's
 //     output buffer and the workgroup barrier orders the passes.
+// The butterflies here are the plain C++ ones: the hand-scheduled statements
+// give wrong words inside these non-inlined task functions (open issue), so
+// this kernel keeps the arithmetic the compiler schedules.
 // Operations: forward (lazy [0, 4q) or canonical), inverse (lazy [0, 2q) or
 // canonical) and the negacyclic product out = a * b of the Section 4 listing
 // (forward(a), forward(b) fused with the multiply, inverse).  The task list
@@ -18,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -27,16 +31,22 @@
 #include "ntt_onchip.h"
 #include "ntt_tile.h"
 
+// Two staging sets are used in turn, so the host can prepare the next batch
+// while the previous one still runs.
+struct ntt_batch_stage {
+  unsigned char* host;             // pinned staging: count word (128-byte line), then the tasks
+  unsigned char* dev;              // device: claim counter (own line), count word, tasks
+  hipEvent_t done;                 // completion of the last run from this set
+  bool pending;
+  hipGraph_t graph;
+  hipGraphExec_t graph_exec;
+};
 struct ntt_batch {
   int device;
   size_t capacity;                 // tasks
-  unsigned char* host;             // pinned staging: count word (128-byte line), then the tasks
-  unsigned char* dev;              // device: claim counter (own line), count word, tasks
-  hipEvent_t done;                 // completion of the last run (staging reuse)
-  bool pending;
   int grid;                        // persistent workgroups (0: automatic)
-  hipGraph_t graph;
-  hipGraphExec_t graph_exec;
+  int cur;                         // staging set of the next run
+  ntt_batch_stage stage[2];
 };
 
 namespace nttamd {
@@ -46,7 +56,8 @@ namespace nttamd {
 // mirrored from byte 128.
 constexpr size_t kStageHead = 128;
 constexpr size_t kDevHead = 128;
-static BatchTask* staged_tasks(ntt_batch* b) { return reinterpret_cast<BatchTask*>(b->host + kStageHead); }
+static ntt_batch_stage& cur_stage(ntt_batch* b) { return b->stage[b->cur]; }
+static BatchTask* staged_tasks(ntt_batch* b) { return reinterpret_cast<BatchTask*>(cur_stage(b).host + kStageHead); }
 static size_t stage_bytes(size_t count) { return kStageHead + count * sizeof(BatchTask); }
 
 constexpr int kBatchThreads = 512;
@@ -58,7 +69,7 @@ template <bool FWD, int LOGN, int MODE>
 __device__ __attribute__((noinline)) void task_onchip(const u64* plan, const u64* in, u64* out, const u64* mul, u32* lds,
                                             bool nt) {
   const PlanView pv = load_plan(plan, FWD, 1ull << LOGN);
-  onchip_body<FWD, LOGN, LOGN - 9, true, MODE>(pv, in, out, mul, lds, nt);
+  onchip_body<FWD, LOGN, LOGN - 9, true, MODE, false>(pv, in, out, mul, lds, nt);
 }
 
 // Both passes of a two-pass transform by one workgroup (512 threads, tiles of
@@ -82,11 +93,11 @@ __device__ __attribute__((noinline)) void task_twopass(const u64* plan, const u6
 #pragma unroll 1
     for (u32 tile = 0; tile < (u32)TILES; ++tile) {
       if (hi) {
-        if (last) tile_body<FWD, LT_HI, 3, LC_HI, 0, MODE, true, -1>(pv, LOGN, LT_LO, tile, src, dst, mul, lds, false);
-        else tile_body<FWD, LT_HI, 3, LC_HI, 0, kOutLazy, false, -1>(pv, LOGN, LT_LO, tile, src, dst, mul, lds, nt);
+        if (last) tile_body<FWD, LT_HI, 3, LC_HI, 0, MODE, true, -1, false>(pv, LOGN, LT_LO, tile, src, dst, mul, lds, false);
+        else tile_body<FWD, LT_HI, 3, LC_HI, 0, kOutLazy, false, -1, false>(pv, LOGN, LT_LO, tile, src, dst, mul, lds, nt);
       } else {
-        if (last) tile_body<FWD, LT_LO, 3, 0, LH_LO, MODE, true, -1>(pv, LOGN, 0, tile, src, dst, mul, lds, false);
-        else tile_body<FWD, LT_LO, 3, 0, LH_LO, kOutLazy, false, -1>(pv, LOGN, 0, tile, src, dst, mul, lds, nt);
+        if (last) tile_body<FWD, LT_LO, 3, 0, LH_LO, MODE, true, -1, false>(pv, LOGN, 0, tile, src, dst, mul, lds, false);
+        else tile_body<FWD, LT_LO, 3, 0, LH_LO, kOutLazy, false, -1, false>(pv, LOGN, 0, tile, src, dst, mul, lds, nt);
       }
       __syncthreads();
     }
@@ -155,9 +166,10 @@ static uint64_t task_cost(uint32_t logN, uint32_t op) {
 }
 
 static ntt_status wait_staging(ntt_batch* b) {
-  if (b->pending) {
-    if (hipEventSynchronize(b->done) != hipSuccess) return NTT_EDEVICE;   // staging still in use
-    b->pending = false;
+  ntt_batch_stage& g = cur_stage(b);
+  if (g.pending) {
+    if (hipEventSynchronize(g.done) != hipSuccess) return NTT_EDEVICE;   // this staging set still in use
+    g.pending = false;
   }
   return NTT_OK;
 }
@@ -196,11 +208,14 @@ ntt_status batch_prepare(ntt_batch* b, const ntt_batch_item* items, size_t count
                    [](const std::pair<uint64_t, size_t>& a, const std::pair<uint64_t, size_t>& c) {
                      return a.first > c.first;
                    });
+  std::map<std::pair<uint64_t, uint64_t>, const ntt_plan*> seen;   // one cache lookup per distinct (N, q)
   for (size_t k = 0; k < count; ++k) {
     const ntt_batch_item& it = items[order[k].second];
-    const ntt_plan* p = nullptr;
-    ntt_status st = cached_plan(it.N, it.q, &p);
-    if (st) return st;
+    const ntt_plan*& p = seen[{it.N, it.q}];
+    if (!p) {
+      ntt_status st = cached_plan(it.N, it.q, &p);
+      if (st) return st;
+    }
     BatchTask& t = staged_tasks(b)[k];
     t.out = it.out;
     t.in = it.in;
@@ -210,7 +225,7 @@ ntt_status batch_prepare(ntt_batch* b, const ntt_batch_item* items, size_t count
     t.logN = (uint32_t)p->logN;
     t.op = it.op;
   }
-  *reinterpret_cast<uint32_t*>(b->host) = (uint32_t)count;
+  *reinterpret_cast<uint32_t*>(cur_stage(b).host) = (uint32_t)count;
   *out_count = count;
   return NTT_OK;
 }
@@ -228,11 +243,12 @@ int batch_grid(const ntt_batch* b, size_t count) {
 
 // Enqueues [descriptor copy of `staged` tasks, counter reset, persistent kernel] on `stream`.
 ntt_status batch_enqueue(ntt_batch* b, size_t staged, int grid, hipStream_t stream) {
-  if (hipMemcpyAsync(b->dev + kDevHead, b->host, stage_bytes(staged), hipMemcpyHostToDevice, stream) != hipSuccess)
+  ntt_batch_stage& g = cur_stage(b);
+  if (hipMemcpyAsync(g.dev + kDevHead, g.host, stage_bytes(staged), hipMemcpyHostToDevice, stream) != hipSuccess)
     return NTT_EDEVICE;
-  u32* counter = reinterpret_cast<u32*>(b->dev);
-  const u32* count = reinterpret_cast<const u32*>(b->dev + kDevHead);
-  const BatchTask* tasks = reinterpret_cast<const BatchTask*>(b->dev + kDevHead + kStageHead);
+  u32* counter = reinterpret_cast<u32*>(g.dev);
+  const u32* count = reinterpret_cast<const u32*>(g.dev + kDevHead);
+  const BatchTask* tasks = reinterpret_cast<const BatchTask*>(g.dev + kDevHead + kStageHead);
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, stream, counter);
   hipLaunchKernelGGL(ntt_batch_kernel, dim3(grid), dim3(kBatchThreads), 0, stream, tasks, count, counter);
   return hipGetLastError() == hipSuccess ? NTT_OK : NTT_EDEVICE;
@@ -240,12 +256,13 @@ ntt_status batch_enqueue(ntt_batch* b, size_t staged, int grid, hipStream_t stre
 
 static ntt_status batch_launch_staged(ntt_batch* b, size_t n, hipStream_t s, bool graph) {
   ntt_status st = NTT_OK;
+  ntt_batch_stage& sg = cur_stage(b);
   if (!graph) {
     st = batch_enqueue(b, n, batch_grid(b, n), s);
     if (st) return st;
   } else {
-    if (!b->graph_exec) {
-      // captured once with the full-capacity copy and grid; the kernel reads the count from device memory
+    if (!sg.graph_exec) {
+      // captured once per staging set with the full-capacity copy and grid; the kernel reads the count from device memory
       const int grid = batch_grid(b, b->capacity);
       hipStream_t cap = nullptr;
       if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return NTT_EDEVICE;
@@ -262,16 +279,17 @@ static ntt_status batch_launch_staged(ntt_batch* b, size_t n, hipStream_t s, boo
         return st;
       }
       if (e != hipSuccess || !g) return NTT_EDEVICE;
-      if (hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      if (hipGraphInstantiate(&sg.graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
         (void)hipGraphDestroy(g);
         return NTT_EDEVICE;
       }
-      b->graph = g;
+      sg.graph = g;
     }
-    if (hipGraphLaunch(b->graph_exec, s) != hipSuccess) return NTT_EDEVICE;
+    if (hipGraphLaunch(sg.graph_exec, s) != hipSuccess) return NTT_EDEVICE;
   }
-  if (hipEventRecord(b->done, s) != hipSuccess) return NTT_EDEVICE;
-  b->pending = true;
+  if (hipEventRecord(sg.done, s) != hipSuccess) return NTT_EDEVICE;
+  sg.pending = true;
+  b->cur ^= 1;
   return NTT_OK;
 }
 
@@ -288,7 +306,7 @@ ntt_status batch_launch_tasks(ntt_batch* b, const BatchTask* tasks, size_t count
                    });
   BatchTask* dst = staged_tasks(b);
   for (size_t k = 0; k < count; ++k) dst[k] = tasks[order[k].second];
-  *reinterpret_cast<uint32_t*>(b->host) = (uint32_t)count;
+  *reinterpret_cast<uint32_t*>(cur_stage(b).host) = (uint32_t)count;
   return batch_launch_staged(b, count, stream, graph);
 }
 
@@ -297,6 +315,16 @@ ntt_status batch_launch_tasks(ntt_batch* b, const BatchTask* tasks, size_t count
 using namespace nttamd;
 
 extern "C" {
+
+static void release_stage(ntt_batch_stage& g) {
+  if (g.pending) (void)hipEventSynchronize(g.done);
+  if (g.graph_exec) (void)hipGraphExecDestroy(g.graph_exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  if (g.done) (void)hipEventDestroy(g.done);
+  if (g.dev) (void)hipFree(g.dev);
+  if (g.host) (void)hipHostFree(g.host);
+  g = ntt_batch_stage{};
+}
 
 ntt_status ntt_batch_create(ntt_batch** out, size_t capacity) {
   if (!out) return NTT_EINVAL_POINTER;
@@ -307,17 +335,16 @@ ntt_status ntt_batch_create(ntt_batch** out, size_t capacity) {
   b->capacity = capacity;
   const size_t bytes = stage_bytes(capacity);
   if (hipGetDevice(&b->device) != hipSuccess) { delete b; return NTT_EDEVICE; }
-  if (hipHostMalloc((void**)&b->host, bytes, hipHostMallocDefault) != hipSuccess) { delete b; return NTT_ENOMEM; }
-  if (hipMalloc((void**)&b->dev, kDevHead + bytes) != hipSuccess) {
-    (void)hipHostFree(b->host);
-    delete b;
-    return NTT_ENOMEM;
-  }
-  if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
-    (void)hipFree(b->dev);
-    (void)hipHostFree(b->host);
-    delete b;
-    return NTT_EDEVICE;
+  for (ntt_batch_stage& g : b->stage) {
+    ntt_status st = NTT_OK;
+    if (hipHostMalloc((void**)&g.host, bytes, hipHostMallocDefault) != hipSuccess) { g.host = nullptr; st = NTT_ENOMEM; }
+    if (!st && hipMalloc((void**)&g.dev, kDevHead + bytes) != hipSuccess) { g.dev = nullptr; st = NTT_ENOMEM; }
+    if (!st && hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess) { g.done = nullptr; st = NTT_EDEVICE; }
+    if (st) {
+      for (ntt_batch_stage& h : b->stage) release_stage(h);
+      delete b;
+      return st;
+    }
   }
   *out = b;
   return NTT_OK;
@@ -325,12 +352,7 @@ ntt_status ntt_batch_create(ntt_batch** out, size_t capacity) {
 
 ntt_status ntt_batch_destroy(ntt_batch* b) {
   if (!b) return NTT_EINVAL_POINTER;
-  if (b->pending) (void)hipEventSynchronize(b->done);
-  if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  (void)hipEventDestroy(b->done);
-  (void)hipFree(b->dev);
-  (void)hipHostFree(b->host);
+  for (ntt_batch_stage& g : b->stage) release_stage(g);
   delete b;
   return NTT_OK;
 }
@@ -338,11 +360,14 @@ ntt_status ntt_batch_destroy(ntt_batch* b) {
 ntt_status ntt_batch_set_grid(ntt_batch* b, int workgroups) {
   if (!b) return NTT_EINVAL_POINTER;
   if (workgroups < 0 || workgroups > (1 << 20)) return NTT_EINVAL_COUNT;
-  if (b->graph_exec && workgroups != b->grid) {   // the captured launch has a fixed grid
-    (void)hipGraphExecDestroy(b->graph_exec);
-    (void)hipGraphDestroy(b->graph);
-    b->graph_exec = nullptr;
-    b->graph = nullptr;
+  for (ntt_batch_stage& g : b->stage) {
+    if (g.graph_exec && workgroups != b->grid) {   // the captured launch has a fixed grid
+      if (g.pending) (void)hipEventSynchronize(g.done);
+      (void)hipGraphExecDestroy(g.graph_exec);
+      (void)hipGraphDestroy(g.graph);
+      g.graph_exec = nullptr;
+      g.graph = nullptr;
+    }
   }
   b->grid = workgroups;
   return NTT_OK;

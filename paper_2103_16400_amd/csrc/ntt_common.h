@@ -43,7 +43,7 @@ struct Geo {
 };
 
 struct PlanView {
-  u64 q, q2, nq;
+  u64 q, q2, nq, nq2;       // nq = 2^64 - q, nq2 = 2^64 - 2q
   u64 ninv, ninv_p, wn, wn_p;
   u64 bk;
   u32 qbits;
@@ -57,6 +57,7 @@ __device__ __forceinline__ PlanView load_plan(const u64* plan, bool fwd, u64 N) 
   v.q = h->q;
   v.q2 = h->q2;
   v.nq = h->nq;
+  v.nq2 = 0 - h->q2;
   v.ninv = h->ninv;
   v.ninv_p = h->ninv_p;
   v.wn = h->wn;

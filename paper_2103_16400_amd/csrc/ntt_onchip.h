@@ -11,7 +11,7 @@
 
 namespace nttamd {
 
-template <bool FWD, int LOGN, int LOGR, bool SPLIT>
+template <bool FWD, int LOGN, int LOGR, bool SPLIT, bool HAND = true>
 struct OnChip {
   static constexpr int N = 1 << LOGN;
   static constexpr int R = 1 << LOGR;
@@ -19,7 +19,9 @@ struct OnChip {
   static constexpr int LDSW = N + (N >> LOGR);
   // transposed sub-tables are laid out for onchip_logr(LOGN) coefficients per thread
   static constexpr int PERM_TOP = LOGR == onchip_logr(LOGN) ? onchip_perm_top(FWD, LOGN) : -1;
-  static constexpr int TB = 2;                      // twiddle pairs per prefetch block
+  // twiddle pairs per prefetch block (one with the hand-scheduled butterflies at
+  // 32 coefficients per thread, to stay within 128 registers)
+  static constexpr int TB = HAND && LOGR >= 5 ? 1 : 2;
   using G = Geo<FWD, LOGN, LOGR>;
   using W = typename std::conditional<SPLIT, u32, u64>::type;
 
@@ -141,9 +143,9 @@ struct OnChip {
           for (int m = 0; m < (1 << p); ++m) {
             const int j = (u << (p + 1)) | m;
             const int j2 = j | (1 << p);
-            if (FWD) harvey_fwd(x[j], x[j2], cur[i].x, cur[i].y, pv.q2, pv.nq);
-            else if (fused_last) harvey_inv_last(x[j], x[j2], pv.ninv, pv.ninv_p, pv.wn, pv.wn_p, pv.q2, pv.nq);
-            else harvey_inv(x[j], x[j2], cur[i].x, cur[i].y, pv.q2, pv.nq);
+            if (FWD) bfly_fwd<HAND>(x[j], x[j2], cur[i].x, cur[i].y, pv.q2, pv.nq, pv.nq2);
+            else if (fused_last) bfly_inv_last<HAND>(x[j], x[j2], pv.ninv, pv.ninv_p, pv.wn, pv.wn_p, pv.q2, pv.nq);
+            else bfly_inv<HAND>(x[j], x[j2], cur[i].x, cur[i].y, pv.q2, pv.nq, pv.nq2);
           }
         }
         stage_fence();
@@ -164,10 +166,10 @@ struct OnChip {
 
 // Transforms one limb: reads `in` (N coefficients), writes `out`; the output
 // step applies MODE with the per-item multiplier / accumulator `mul`.
-template <bool FWD, int LOGN, int LOGR, bool SPLIT, int MODE>
+template <bool FWD, int LOGN, int LOGR, bool SPLIT, int MODE, bool HAND = true>
 __device__ __forceinline__ void onchip_body(const PlanView& pv, const u64* in, u64* out, const u64* mul,
-                                            typename OnChip<FWD, LOGN, LOGR, SPLIT>::W* lds, bool nt_load) {
-  using K = OnChip<FWD, LOGN, LOGR, SPLIT>;
+                                            typename OnChip<FWD, LOGN, LOGR, SPLIT, HAND>::W* lds, bool nt_load) {
+  using K = OnChip<FWD, LOGN, LOGR, SPLIT, HAND>;
   constexpr int R = K::R;
   constexpr int NT = K::NT;
   constexpr int RL = K::G::NR - 1;

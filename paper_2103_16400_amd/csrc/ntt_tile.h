@@ -10,7 +10,7 @@
 
 namespace nttamd {
 
-template <bool FWD, int LOGT, int LOGR, int LOGC, int LOGH>
+template <bool FWD, int LOGT, int LOGR, int LOGC, int LOGH, bool HAND = true>
 struct TileNtt {
   static constexpr int R = 1 << LOGR;
   static constexpr int C = 1 << LOGC;
@@ -120,9 +120,9 @@ struct TileNtt {
           for (int m = 0; m < (1 << p); ++m) {
             const int j = (u << (p + 1)) | m;
             const int j2 = j | (1 << p);
-            if (FWD) harvey_fwd(x[j], x[j2], cur[i].x, cur[i].y, pv.q2, pv.nq);
-            else if (fused_last) harvey_inv_last(x[j], x[j2], pv.ninv, pv.ninv_p, pv.wn, pv.wn_p, pv.q2, pv.nq);
-            else harvey_inv(x[j], x[j2], cur[i].x, cur[i].y, pv.q2, pv.nq);
+            if (FWD) bfly_fwd<HAND>(x[j], x[j2], cur[i].x, cur[i].y, pv.q2, pv.nq, pv.nq2);
+            else if (fused_last) bfly_inv_last<HAND>(x[j], x[j2], pv.ninv, pv.ninv_p, pv.wn, pv.wn_p, pv.q2, pv.nq);
+            else bfly_inv<HAND>(x[j], x[j2], cur[i].x, cur[i].y, pv.q2, pv.nq, pv.nq2);
           }
         }
         stage_fence();
@@ -144,10 +144,10 @@ struct TileNtt {
 
 // Runs one tile of one pass.  in/out/mul point at the limb's first coefficient;
 // `tile` selects the tile inside the limb; b0 = lowest index bit of the pass.
-template <bool FWD, int LOGT, int LOGR, int LOGC, int LOGH, int MODE, bool LASTPASS, int PTOP>
+template <bool FWD, int LOGT, int LOGR, int LOGC, int LOGH, int MODE, bool LASTPASS, int PTOP, bool HAND = true>
 __device__ __forceinline__ void tile_body(const PlanView& pv, u32 logN, u32 b0, u32 tile, const u64* in_item,
                                           u64* out_item, const u64* mul, u64* lds, bool nt_load) {
-  using K = TileNtt<FWD, LOGT, LOGR, LOGC, LOGH>;
+  using K = TileNtt<FWD, LOGT, LOGR, LOGC, LOGH, HAND>;
   constexpr int R = K::R;
   constexpr int C = K::C;
   constexpr int NT = K::NT;
