@@ -38,9 +38,9 @@ HBM_PEAK_GBS = 8000.0
 # read 524300 KiB for 1048576 KiB copied: x2.0; WRITE_SIZE read 1048576 KiB: x1.0).  Valid only for
 # the kernel sources they were taken with, identified by the SHA-256 of these files.
 TRAFFIC_FWD_N16384 = {
-    "fetch_kib": 275576.5, "fetch_scale": 2.0, "write_kib": 524288.0, "write_scale": 1.0,
+    "fetch_kib": 275674.9, "fetch_scale": 2.0, "write_kib": 524288.2, "write_scale": 1.0,
     "sources": ["ntt_onchip.hip", "ntt_onchip.h", "ntt_common.h", "modarith.h"],
-    "sha256": "0d81557cc8ca152cced2836837c7cb76d7cba4deeb87ea4524a1bf38e06ca057",
+    "sha256": "b36ec01057fa906d2188a47427f1000dbad5b5e597423de5626d9754ef0ce7a0",
 }
 
 
@@ -362,14 +362,18 @@ def main():
 
     def step(record):
         if record:
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
+            es = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            es[0].record(stream)
         nt.ntt_forward_rns(c, a, N, moduli, B, 1, 4, stream=stream)             # c = NTT(a), lazy [0, 4q)
         if record:
-            e1.record(stream)
-            ev.append((e0, e1))
+            es[1].record(stream)
         nt.ntt_forward_mul_rns(c, b, c, N, moduli, B, 1, ws, stream=stream)      # c = NTT(b) (.) c
+        if record:
+            es[2].record(stream)
         nt.ntt_inverse_acc_rns(acc, c, N, moduli, B, 1, ws, stream=stream)      # acc += InvNTT(c)
+        if record:
+            es[3].record(stream)
+            ev.append(es)
 
     for _ in range(args.warmup):
         step(False)
@@ -380,7 +384,9 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
-    fwd_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in ev]))
+    fwd_ms = float(np.mean([es[0].elapsed_time(es[1]) for es in ev]))
+    fwd_mul_ms = float(np.mean([es[1].elapsed_time(es[2]) for es in ev]))
+    inv_acc_ms = float(np.mean([es[2].elapsed_time(es[3]) for es in ev]))
 
     limbs = B * L
     fwd_per_step = 2 * limbs
@@ -409,6 +415,8 @@ def main():
                      "traffic": measured_traffic(TRAFFIC_FWD_N16384) if (N, limbs) == (16384, 4096) else None,
                      "kernel": "ntt_onchip_kernel<fwd, N=2^14>: forward NTT of %d limbs, one launch" % limbs,
                      "avg_ms": round(fwd_ms, 4), "alg_bytes": alg_bytes},
+        "step_kernels_ms": {"fwd_lazy": round(fwd_ms, 4), "fwd_mul": round(fwd_mul_ms, 4),
+                            "inv_acc": round(inv_acc_ms, 4)},
         "fwd_ntt_rate": round(limbs / (fwd_ms * 1e-3), 1),
         "products_per_s": round(limbs / (wall / args.steps), 1),
     }

@@ -19,9 +19,9 @@ struct OnChip {
   static constexpr int LDSW = N + (N >> LOGR);
   // transposed sub-tables are laid out for onchip_logr(LOGN) coefficients per thread
   static constexpr int PERM_TOP = LOGR == onchip_logr(LOGN) ? onchip_perm_top(FWD, LOGN) : -1;
-  // twiddle pairs per prefetch block (one with the hand-scheduled butterflies at
-  // 32 coefficients per thread, to stay within 128 registers)
-  static constexpr int TB = HAND && LOGR >= 5 ? 1 : 2;
+  // twiddle pairs per prefetch block (one for the hand-scheduled forward at 32
+  // coefficients per thread, which needs the registers to stay within 128)
+  static constexpr int TB = HAND && FWD && LOGR >= 5 ? 1 : 2;
   using G = Geo<FWD, LOGN, LOGR>;
   using W = typename std::conditional<SPLIT, u32, u64>::type;
 
