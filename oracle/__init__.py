@@ -38,6 +38,9 @@ def lib():
             ("or_find_primes_up", _U64, [ctypes.c_int, _U64, _U64, _U64P]),
             ("or_eltwise_add", None, [_U64P, _U64P, _U64P, _U64, _U64]),
             ("or_eltwise_mult", None, [_U64P, _U64P, _U64P, _U64, _U64]),
+            ("or_eltwise_fma", None, [_U64P, _U64P, _U64, ctypes.c_void_p, _U64, _U64]),
+            ("or_eltwise_sub", None, [_U64P, _U64P, _U64P, _U64, _U64]),
+            ("or_eltwise_negate", None, [_U64P, _U64P, _U64, _U64]),
             ("or_ntt_forward", None, [_U64P, _U64P, _U64, _U64, _U64, ctypes.c_int]),
             ("or_ntt_inverse", None, [_U64P, _U64P, _U64, _U64, _U64, ctypes.c_int]),
             ("or_ntt_forward_at", None, [_U64P, _U64P, _U64P, _U64, _U64, _U64, _U64, ctypes.c_int]),
@@ -100,6 +103,32 @@ def eltwise_mult(a, b, q):
     a, b = _arr(a), _arr(b)
     c = np.empty_like(a)
     lib().or_eltwise_mult(_p(c), _p(a), _p(b), a.size, q)
+    return c
+
+
+def eltwise_fma(a, y, z, q):
+    """(a_i * y + z_i) mod q; z may be None (no addition)."""
+    a = _arr(a)
+    c = np.empty_like(a)
+    zp = None
+    if z is not None:
+        z = _arr(z)
+        zp = z.ctypes.data
+    lib().or_eltwise_fma(_p(c), _p(a), y, zp, a.size, q)
+    return c
+
+
+def eltwise_sub(a, b, q):
+    a, b = _arr(a), _arr(b)
+    c = np.empty_like(a)
+    lib().or_eltwise_sub(_p(c), _p(a), _p(b), a.size, q)
+    return c
+
+
+def eltwise_negate(a, q):
+    a = _arr(a)
+    c = np.empty_like(a)
+    lib().or_eltwise_negate(_p(c), _p(a), a.size, q)
     return c
 
 

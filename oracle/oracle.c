@@ -18,7 +18,9 @@
  *     accumulation cannot change any output.
  *
  * Definitions implemented (all from Section 2 of the paper):
- *   - element-wise add / multiply (Section 2, list of ring operations);
+ *   - element-wise add / multiply / subtract / negate and the vector-scalar
+ *     fused multiply-add (Section 2, list of ring operations; Section 4
+ *     free-function listing);
  *   - negacyclic product c_i = sum_{j<=i} a_j b_{i-j} - sum_{j>i} a_j b_{N+i-j}
  *     (Section 2, "vector-vector multiplication");
  *   - negacyclic forward NTT with bit-reversed output (Section 2.2: cyclic NTT
@@ -146,6 +148,29 @@ void or_eltwise_add(uint64_t* c, const uint64_t* a, const uint64_t* b, uint64_t 
 /* c_i = (a_i * b_i) mod q; inputs are interpreted modulo q. */
 void or_eltwise_mult(uint64_t* c, const uint64_t* a, const uint64_t* b, uint64_t n, uint64_t q) {
   for (uint64_t i = 0; i < n; ++i) c[i] = or_mulmod(a[i] % q, b[i] % q, q);
+}
+
+/* c_i = (a_i * y + z_i) mod q, the fused multiply-add of the free-function
+ * listing of Section 4 (vector-scalar multiplication of Section 2 plus an
+ * optional vector addition: z == NULL adds nothing).  Inputs are interpreted
+ * modulo q. */
+void or_eltwise_fma(uint64_t* c, const uint64_t* a, uint64_t y, const uint64_t* z, uint64_t n, uint64_t q) {
+  for (uint64_t i = 0; i < n; ++i) {
+    u128 v = (u128)(a[i] % q) * (y % q);
+    if (z) v += z[i] % q;
+    c[i] = (uint64_t)(v % q);
+  }
+}
+
+/* c_i = (a_i - b_i) mod q in [0, q); inputs are interpreted modulo q. */
+void or_eltwise_sub(uint64_t* c, const uint64_t* a, const uint64_t* b, uint64_t n, uint64_t q) {
+  for (uint64_t i = 0; i < n; ++i) c[i] = (uint64_t)(((u128)(a[i] % q) + q - (b[i] % q)) % q);
+}
+
+/* c_i = -a_i mod q in [0, q) (Section 2, element-wise negation q - a_i, with
+ * the zero residue kept at 0); inputs are interpreted modulo q. */
+void or_eltwise_negate(uint64_t* c, const uint64_t* a, uint64_t n, uint64_t q) {
+  for (uint64_t i = 0; i < n; ++i) c[i] = (uint64_t)((q - (a[i] % q)) % q);
 }
 
 /* ---- direct O(N^2) transforms (Section 2.2 definitions) ------------------ */
