@@ -192,7 +192,7 @@ def time_uneven_batch(nt, torch, primes, reps=10):
     return res
 
 
-SERVE_RATES = (1000, 2000, 5000, 10000, 20000, 50000)
+SERVE_RATES = (1000, 2000, 5000, 10000, 20000, 30000, 40000, 50000)
 
 
 class OperandPool:
@@ -229,10 +229,11 @@ def serve_schedule(rate, n):
     return offs, logNs, Ls
 
 
-def run_served(nt, pool, moduli, mode, rate, n, streams=2):
+def run_served(nt, pool, moduli, mode, rate, n, streams=2, wide_min=0, wide_max=0):
     """One open-loop run; latency = completion seen by the scheduler - scheduled arrival."""
     offs, logNs, Ls = serve_schedule(rate, n)
-    srv = nt.Server(mode=mode, streams=streams, release_on_completion=True)
+    srv = nt.Server(mode=mode, streams=streams, release_on_completion=True, wide_min_log_degree=wide_min,
+                    wide_max_inflight=wide_max)
     for logN in range(12, 18):                   # warm-up: plans of every (N, q) and the kernels
         a, b = pool.pick(logN, 0)
         srv.submit(a, b, 1 << logN, moduli)
@@ -257,18 +258,26 @@ def run_served(nt, pool, moduli, mode, rate, n, streams=2):
 
 
 def time_serving(nt, torch, primes, rates=SERVE_RATES, max_requests=4000, seconds=1.0,
-                 modes=("batched", "fifo", "fifo_per_limb")):
+                 modes=("batched", "batched_persistent_only", "fifo", "fifo_per_limb")):
+    """Open-loop sweep over arrival rates for each serving form; the per-limb FIFO form (about 850
+    req/s at best) is swept only up to 5k req/s, where it is already saturated."""
     moduli = primes["serving"]["moduli"]
     pool = OperandPool(torch, moduli)
-    code = {"batched": nt.SERVE_BATCHED, "fifo": nt.SERVE_FIFO, "fifo_per_limb": nt.SERVE_FIFO_PER_LIMB}
+    code = {"batched": (nt.SERVE_BATCHED, 0, 0), "batched_persistent_only": (nt.SERVE_BATCHED, 18, 0),
+            "fifo": (nt.SERVE_FIFO, 0, 0), "fifo_per_limb": (nt.SERVE_FIFO_PER_LIMB, 0, 0)}
+    for m in modes:
+        if m.startswith("batched_cap"):
+            code[m] = (nt.SERVE_BATCHED, 0, int(m[len("batched_cap"):]))
     res = {"workload": "Poisson stream of negacyclic products, N ~ U{2^12..2^17}, L ~ U[1,40] "
                        "(50-60-bit primes), operands resident",
            "requests_per_rate": "min(%d, rate x %.1f s)" % (max_requests, seconds)}
     for m in modes:
         runs = []
         for r in rates:
+            if m == "fifo_per_limb" and r > 5000:
+                continue
             n = int(min(max_requests, r * seconds))
-            runs.append(run_served(nt, pool, moduli, code[m], r, n))
+            runs.append(run_served(nt, pool, moduli, code[m][0], r, n, wide_min=code[m][1], wide_max=code[m][2]))
             print("serve %s rate %d: p50 %.2f ms p99 %.2f ms, %.0f req/s" %
                   (m, r, runs[-1]["p50_ms"], runs[-1]["p99_ms"], runs[-1]["throughput_rps"]), file=sys.stderr,
                   flush=True)
@@ -317,6 +326,8 @@ def main():
     ap.add_argument("--serve-only", action="store_true", help="run only the serving sweep (full size)")
     ap.add_argument("--serve-requests", type=int, default=4000, help="cap on requests per arrival rate")
     ap.add_argument("--serve-seconds", type=float, default=1.0, help="arrival window per rate")
+    ap.add_argument("--serve-modes", default="batched,batched_persistent_only,fifo,fifo_per_limb",
+                    help="comma-separated serving forms (batched_capK: batched with K wide launches per stream)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 4 times (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -340,7 +351,8 @@ def main():
 
     if args.serve_only:
         print(json.dumps({"serving": time_serving(nt, torch, load_primes(), max_requests=args.serve_requests,
-                                                  seconds=args.serve_seconds)}), flush=True)
+                                                  seconds=args.serve_seconds,
+                                                  modes=tuple(args.serve_modes.split(",")))}), flush=True)
         return
 
     primes = load_primes()["rns_16384"]
@@ -428,7 +440,7 @@ def main():
         out["uneven_batch_256polys"] = time_uneven_batch(nt, torch, load_primes())
         if not args.no_serve:
             out["serving"] = time_serving(nt, torch, load_primes(), max_requests=args.serve_requests,
-                                          seconds=args.serve_seconds)
+                                          seconds=args.serve_seconds, modes=tuple(args.serve_modes.split(",")))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, moduli, psis, args.cpu_seconds)
     print(json.dumps(out), flush=True)

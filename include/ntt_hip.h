@@ -142,6 +142,35 @@ ntt_status eltwise_add_mod(uint64_t* result, const uint64_t* operand1, const uin
                            uint64_t n, uint64_t modulus, ntt_stream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Vector-scalar fused multiply-add: the EltwiseFMAMod free function of the
+ * Section 4 listing, computed as in Algorithm 10 (inputs reduced to [0, q),
+ * Shoup product with the scalar's precomputed companion, then the addition):
+ *   result[i] = (arg1[i] * arg2 + arg3[i]) mod q, canonical in [0, q).
+ * arg3 may be NULL (no addition).  arg1 and arg3 values in
+ * [0, input_mod_factor * q), input_mod_factor in {1, 2, 4, 8}
+ * (NTT_EINVAL_FACTOR otherwise); modulus in [2, 2^61 - 1] (NTT_EINVAL_MODULUS);
+ * the scalar is taken modulo q.  result may equal arg1 and/or arg3 exactly.
+ * eltwise_fma_mod_rns: the same on num_polys x num_limbs limbs of N elements
+ * ([(p L + l) N + i]); arg2 is a host array of num_limbs scalars (one per
+ * limb), moduli a host array of num_limbs moduli.
+ */
+ntt_status eltwise_fma_mod(uint64_t* result, const uint64_t* arg1, uint64_t arg2, const uint64_t* arg3, uint64_t n,
+                           uint64_t modulus, uint64_t input_mod_factor, ntt_stream_t stream);
+ntt_status eltwise_fma_mod_rns(uint64_t* result, const uint64_t* arg1, const uint64_t* arg2, const uint64_t* arg3,
+                               uint64_t N, const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
+                               uint64_t input_mod_factor, ntt_stream_t stream);
+
+/* Element-wise subtraction and negation (Section 2 ring operations):
+ *   eltwise_sub_mod:    result[i] = (operand1[i] - operand2[i]) mod q,
+ *   eltwise_negate_mod: result[i] = (q - operand[i]) mod q (0 stays 0),
+ * operands in [0, q), results canonical; modulus in [2, 2^63 - 1].  result may
+ * equal an operand exactly. */
+ntt_status eltwise_sub_mod(uint64_t* result, const uint64_t* operand1, const uint64_t* operand2, uint64_t n,
+                           uint64_t modulus, ntt_stream_t stream);
+ntt_status eltwise_negate_mod(uint64_t* result, const uint64_t* operand, uint64_t n, uint64_t modulus,
+                              ntt_stream_t stream);
+
+/* ---------------------------------------------------------------------------
  * RNS batches (Section 5: a polynomial modulo Q = q_0 ... q_{L-1} is held as
  * L residue polynomials, one per word-sized prime, processed limb by limb).
  * Layout: num_polys polynomials, each num_limbs limbs of N coefficients,
@@ -307,7 +336,14 @@ ntt_status ntt_set_variant(uint64_t N, uint64_t num_items, int forward, int vari
  *     the next persistent batch launch (one task per limb product, largest
  *     first), with up to `streams` launches in flight on separate streams, so
  *     requests that arrive while others run join the next launch and its work
- *     overlaps the tail of the running one;
+ *     overlaps the tail of the running one.  Requests with N at or above
+ *     2^wide_min_log_degree instead run as their own three launches of the
+ *     two-pass kernels (forward, forward fused with the multiply, inverse),
+ *     round robin over `streams` further streams, overlapping the rest, as
+ *     long as fewer than wide_max_inflight such launches per wide stream are
+ *     in flight;
+ *     beyond that they join the persistent launches (which pack the chip
+ *     better under load);
  *   - NTT_SERVE_FIFO: each request alone, in arrival order on one stream,
  *     as three launches over its limbs (forward, forward fused with the
  *     multiply, inverse);
@@ -325,6 +361,8 @@ ntt_status ntt_set_variant(uint64_t N, uint64_t num_items, int forward, int vari
  *   max_queue 0 = 2^20 requests submitted but not yet admitted.
  *   release_on_completion != 0 returns a request's arena space as soon as it
  *   completes (for load generation: the result is then not kept).
+ *   NTT_EINVAL_COUNT for a mode, stream count, task cap, wide_min_log_degree
+ *   (10..18) or wide_max_inflight out of range.
  * ntt_server_submit: validates and queues; plans for new (N, q) are built on
  *   the calling thread, which must have the server's device current
  *   (NTT_EDEVICE otherwise).  Errors: NTT_EINVAL_POINTER (null a, b, moduli,
@@ -361,6 +399,11 @@ typedef struct {
   uint32_t max_queue;
   uint32_t release_on_completion;
   uint32_t use_graph;       /* nonzero: batched launches replay a captured hipGraph */
+  uint32_t wide_min_log_degree;  /* batched mode: requests with N >= 2^this run as their own
+                                    launches of the two-pass kernels on `streams` extra streams;
+                                    0 = 15, 18 = never (all requests in persistent launches) */
+  uint32_t wide_max_inflight;    /* such launches in flight per wide stream before further large
+                                    requests join the persistent launches; 0 = 8, at most 1024 */
 } ntt_server_config;
 typedef struct {
   uint64_t N;

@@ -55,6 +55,10 @@ _SIGS = {
     "ntt_batch_run": (_ST, [_P, _P, ctypes.c_size_t, _P]),
     "ntt_batch_run_graph": (_ST, [_P, _P, ctypes.c_size_t, _P]),
     "ntt_batch_autotune": (_ST, [_P, _P, ctypes.c_size_t, _P, ctypes.POINTER(ctypes.c_int)]),
+    "eltwise_fma_mod": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _P]),
+    "eltwise_fma_mod_rns": (_ST, [_P, _P, _P, _P, _U64, _P, _U64, _U64, _U64, _P]),
+    "eltwise_sub_mod": (_ST, [_P, _P, _P, _U64, _U64, _P]),
+    "eltwise_negate_mod": (_ST, [_P, _P, _U64, _U64, _P]),
     "ntt_server_create": (_ST, [ctypes.POINTER(_P), _P]),
     "ntt_server_submit": (_ST, [_P, _P, ctypes.POINTER(_U64)]),
     "ntt_server_poll": (_ST, [_P, _U64, _P]),
@@ -308,11 +312,36 @@ class Batch:
         _check(fn(self._h, items, count, _stream(stream)), "ntt_batch_run_graph" if graph else "ntt_batch_run")
 
 
+def eltwise_fma_mod(result, arg1, arg2, arg3, n, modulus, input_mod_factor=1, stream=None):
+    """result = (arg1 * arg2 + arg3) mod q (arg3 may be None); Algorithm 10."""
+    _check(_lib.eltwise_fma_mod(_ptr(result), _ptr(arg1), int(arg2), _ptr(arg3), n, modulus, input_mod_factor,
+                                _stream(stream)), "eltwise_fma_mod")
+
+
+def eltwise_fma_mod_rns(result, arg1, scalars, arg3, N, moduli, num_polys, input_mod_factor=1, stream=None):
+    m, L = _moduli(moduli)
+    y, Ly = _moduli(scalars)
+    if Ly != L:
+        raise ValueError("one scalar per limb expected")
+    _check(_lib.eltwise_fma_mod_rns(_ptr(result), _ptr(arg1), y, _ptr(arg3), N, m, L, num_polys, input_mod_factor,
+                                    _stream(stream)), "eltwise_fma_mod_rns")
+
+
+def eltwise_sub_mod(result, operand1, operand2, n, modulus, stream=None):
+    _check(_lib.eltwise_sub_mod(_ptr(result), _ptr(operand1), _ptr(operand2), n, modulus, _stream(stream)),
+           "eltwise_sub_mod")
+
+
+def eltwise_negate_mod(result, operand, n, modulus, stream=None):
+    _check(_lib.eltwise_negate_mod(_ptr(result), _ptr(operand), n, modulus, _stream(stream)), "eltwise_negate_mod")
+
+
 class ServerConfig(ctypes.Structure):
     """ntt_server_config of include/ntt_hip.h."""
     _fields_ = [("hbm_budget", _U64), ("mode", ctypes.c_uint32), ("streams", ctypes.c_uint32),
                 ("max_batch_tasks", ctypes.c_uint32), ("max_queue", ctypes.c_uint32),
-                ("release_on_completion", ctypes.c_uint32), ("use_graph", ctypes.c_uint32)]
+                ("release_on_completion", ctypes.c_uint32), ("use_graph", ctypes.c_uint32),
+                ("wide_min_log_degree", ctypes.c_uint32), ("wide_max_inflight", ctypes.c_uint32)]
 
 
 class Request(ctypes.Structure):
@@ -346,9 +375,9 @@ class Server:
     """Continuous-batching server for negacyclic products (ntt_server_* of include/ntt_hip.h)."""
 
     def __init__(self, hbm_budget=0, mode=SERVE_BATCHED, streams=0, max_batch_tasks=0, max_queue=0,
-                 release_on_completion=False, use_graph=False):
+                 release_on_completion=False, use_graph=False, wide_min_log_degree=0, wide_max_inflight=0):
         cfg = ServerConfig(hbm_budget, mode, streams, max_batch_tasks, max_queue, int(bool(release_on_completion)),
-                           int(bool(use_graph)))
+                           int(bool(use_graph)), wide_min_log_degree, wide_max_inflight)
         h = _P()
         _check(_lib.ntt_server_create(ctypes.byref(h), ctypes.byref(cfg)), "ntt_server_create")
         self._h = h

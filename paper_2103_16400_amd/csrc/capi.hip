@@ -95,6 +95,45 @@ ntt_status elt_rns(bool mult, uint64_t* result, const uint64_t* a, const uint64_
   return mult ? launch_eltwise_mult(l) : launch_eltwise_add(l);
 }
 
+ntt_status fma_rns(uint64_t* result, const uint64_t* a, const uint64_t* scalars, const uint64_t* z, uint64_t N,
+                   const uint64_t* moduli, uint64_t L, uint64_t B, uint64_t in_f, ntt_stream_t stream) {
+  if (!result || !a || !scalars || !moduli) return NTT_EINVAL_POINTER;
+  if (N == 0 || B == 0 || L == 0 || L > NTT_MAX_LIMBS) return NTT_EINVAL_COUNT;
+  if (B > (1ull << 40) / (L * N)) return NTT_EINVAL_COUNT;
+  if (in_f != 1 && in_f != 2 && in_f != 4 && in_f != 8) return NTT_EINVAL_FACTOR;
+  for (uint64_t i = 0; i < L; ++i)
+    if (moduli[i] < 2 || moduli[i] > (1ull << 61) - 1) return NTT_EINVAL_MODULUS;
+  const size_t bytes = (size_t)(B * L * N * sizeof(uint64_t));
+  ntt_status st = check_alias(result, a, bytes);
+  if (st) return st;
+  if (z) {
+    st = check_alias(result, z, bytes);
+    if (st) return st;
+  }
+  EltLaunch l{result, a, z, N, moduli, (uint32_t)L, B, (uint32_t)in_f, (hipStream_t)stream, scalars};
+  return launch_eltwise_fma(l);
+}
+
+ntt_status sub_rns(bool negate, uint64_t* result, const uint64_t* a, const uint64_t* b, uint64_t N,
+                   const uint64_t* moduli, uint64_t L, uint64_t B, ntt_stream_t stream) {
+  if (!result || !a || (!negate && !b) || !moduli) return NTT_EINVAL_POINTER;
+  if (N == 0 || B == 0 || L == 0 || L > NTT_MAX_LIMBS) return NTT_EINVAL_COUNT;
+  if (B > (1ull << 40) / (L * N)) return NTT_EINVAL_COUNT;
+  for (uint64_t i = 0; i < L; ++i) {
+    ntt_status st = check_add_modulus(moduli[i]);
+    if (st) return st;
+  }
+  const size_t bytes = (size_t)(B * L * N * sizeof(uint64_t));
+  ntt_status st = check_alias(result, a, bytes);
+  if (st) return st;
+  if (!negate) {
+    st = check_alias(result, b, bytes);
+    if (st) return st;
+  }
+  EltLaunch l{result, a, negate ? nullptr : b, N, moduli, (uint32_t)L, B, 1, (hipStream_t)stream, nullptr};
+  return launch_eltwise_sub(l, negate);
+}
+
 }  // namespace
 
 extern "C" {
@@ -176,6 +215,27 @@ ntt_status eltwise_mult_mod(uint64_t* result, const uint64_t* operand1, const ui
 ntt_status eltwise_add_mod(uint64_t* result, const uint64_t* operand1, const uint64_t* operand2, uint64_t n,
                            uint64_t modulus, ntt_stream_t stream) {
   return elt_rns(false, result, operand1, operand2, n, &modulus, 1, 1, 1, stream);
+}
+
+ntt_status eltwise_fma_mod(uint64_t* result, const uint64_t* arg1, uint64_t arg2, const uint64_t* arg3, uint64_t n,
+                           uint64_t modulus, uint64_t input_mod_factor, ntt_stream_t stream) {
+  return fma_rns(result, arg1, &arg2, arg3, n, &modulus, 1, 1, input_mod_factor, stream);
+}
+
+ntt_status eltwise_fma_mod_rns(uint64_t* result, const uint64_t* arg1, const uint64_t* arg2, const uint64_t* arg3,
+                               uint64_t N, const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
+                               uint64_t input_mod_factor, ntt_stream_t stream) {
+  return fma_rns(result, arg1, arg2, arg3, N, moduli, num_limbs, num_polys, input_mod_factor, stream);
+}
+
+ntt_status eltwise_sub_mod(uint64_t* result, const uint64_t* operand1, const uint64_t* operand2, uint64_t n,
+                           uint64_t modulus, ntt_stream_t stream) {
+  return sub_rns(false, result, operand1, operand2, n, &modulus, 1, 1, stream);
+}
+
+ntt_status eltwise_negate_mod(uint64_t* result, const uint64_t* operand, uint64_t n, uint64_t modulus,
+                              ntt_stream_t stream) {
+  return sub_rns(true, result, operand, nullptr, n, &modulus, 1, 1, stream);
 }
 
 ntt_status ntt_forward_rns(uint64_t* result, const uint64_t* operand, uint64_t N, const uint64_t* moduli,

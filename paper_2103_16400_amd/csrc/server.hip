@@ -7,8 +7,11 @@
 //   future   -- submitted, arrival time not reached (min-heap on arrival);
 //   ready    -- arrived, waiting for arena space (arrival order);
 //   admitted -- arena space reserved, not launched;
-// launches in flight sit in stream slots (batched mode) or in an in-order
-// list of per-request events (FIFO modes).  Host time stamps use the
+// launches in flight sit in stream slots (persistent batch launches), in a
+// list of per-request events on the wide streams (batched mode, large rings:
+// a limb product of N >= 2^15 inside one workgroup would take milliseconds,
+// while the two-pass kernels spread it over the chip), or in an in-order list
+// of per-request events (FIFO modes).  Host time stamps use the
 // monotonic clock; a request's completion time is taken when the scheduler
 // sees the event of the launch holding it complete (it polls while work is
 // in flight).
@@ -139,7 +142,11 @@ struct ntt_server {
   std::unordered_map<uint64_t, std::unique_ptr<Req>> records;
   std::priority_queue<Req*, std::vector<Req*>, LaterArrival> future;
   std::deque<Req*> ready;
-  std::deque<Req*> admitted;
+  std::deque<Req*> admitted;        // to the persistent batch launches
+  std::deque<Req*> admitted_wide;   // batched mode, N >= 2^wide_min: own launches on the wide streams
+  std::vector<hipStream_t> wide;
+  size_t wide_rr = 0;
+  std::vector<std::pair<hipEvent_t, Req*>> wide_inflight;
   std::vector<Slot> slots;
   std::deque<std::pair<hipEvent_t, Req*>> fifo_inflight;
   std::vector<hipEvent_t> event_pool;
@@ -202,7 +209,8 @@ void admit(ntt_server* s) {
     }
     r->state = NTT_REQ_ADMITTED;
     r->admit = clock_ns();
-    s->admitted.push_back(r);
+    if (s->cfg.mode == NTT_SERVE_BATCHED && r->logN >= s->cfg.wide_min_log_degree) s->admitted_wide.push_back(r);
+    else s->admitted.push_back(r);
     s->ready.pop_front();
   }
 }
@@ -290,6 +298,40 @@ ntt_status enqueue_per_limb(ntt_server* s, Req* r, hipStream_t stream) {
 bool launch(ntt_server* s) {
   bool any = false;
   if (s->cfg.mode == NTT_SERVE_BATCHED) {
+    // large rings: the wide two-pass kernels, three launches over the request's limbs,
+    // round robin over the wide streams (they overlap the persistent launches)
+    // While the wide streams already hold wide_max_inflight launches each, further large
+    // requests join the persistent launches instead: under load the packed
+    // launch keeps the chip fuller than more separate launches would.
+    const size_t wide_cap = (size_t)s->cfg.wide_max_inflight * s->wide.size();
+    while (!s->admitted_wide.empty() && s->wide_inflight.size() >= wide_cap) {
+      s->admitted.push_back(s->admitted_wide.front());
+      s->admitted_wide.pop_front();
+    }
+    while (!s->admitted_wide.empty()) {
+      Req* r = s->admitted_wide.front();
+      s->admitted_wide.pop_front();
+      hipStream_t ws = s->wide[s->wide_rr++ % s->wide.size()];
+      r->state = NTT_REQ_RUNNING;
+      r->launch = clock_ns();
+      ntt_status e = enqueue_fused(s, r, ws);
+      hipEvent_t ev = e ? nullptr : take_event(s);
+      if (!e && (!ev || hipEventRecord(ev, ws) != hipSuccess)) e = NTT_EDEVICE;
+      if (e) {
+        if (ev) s->event_pool.push_back(ev);
+        finish(s, r, clock_ns(), e);
+        s->cv_done.notify_all();
+        continue;
+      }
+      s->wide_inflight.emplace_back(ev, r);
+      ++s->st.launches;
+      s->st.tasks += r->L;
+      any = true;
+      while (!s->admitted_wide.empty() && s->wide_inflight.size() >= wide_cap) {
+        s->admitted.push_back(s->admitted_wide.front());
+        s->admitted_wide.pop_front();
+      }
+    }
     const size_t cap = s->cfg.max_batch_tasks;
     for (Slot& sl : s->slots) {
       if (s->admitted.empty()) break;
@@ -369,6 +411,19 @@ bool reap(ntt_server* s) {
     sl.busy = false;
     any = true;
   }
+  for (size_t i = 0; i < s->wide_inflight.size();) {
+    auto& f = s->wide_inflight[i];
+    const hipError_t q = hipEventQuery(f.first);
+    if (q == hipErrorNotReady) {
+      ++i;
+      continue;
+    }
+    finish(s, f.second, clock_ns(), q == hipSuccess ? NTT_OK : NTT_EDEVICE);
+    s->event_pool.push_back(f.first);
+    f = s->wide_inflight.back();
+    s->wide_inflight.pop_back();
+    any = true;
+  }
   while (!s->fifo_inflight.empty()) {
     auto& f = s->fifo_inflight.front();
     const hipError_t q = hipEventQuery(f.first);
@@ -383,7 +438,7 @@ bool reap(ntt_server* s) {
 }
 
 bool in_flight(const ntt_server* s) {
-  if (!s->fifo_inflight.empty()) return true;
+  if (!s->fifo_inflight.empty() || !s->wide_inflight.empty()) return true;
   for (const Slot& sl : s->slots)
     if (sl.busy) return true;
   return false;
@@ -399,6 +454,8 @@ void cancel_pending(ntt_server* s) {
   s->ready.clear();
   for (Req* r : s->admitted) finish(s, r, t, NTT_EBUSY);
   s->admitted.clear();
+  for (Req* r : s->admitted_wide) finish(s, r, t, NTT_EBUSY);
+  s->admitted_wide.clear();
   s->cv_done.notify_all();
 }
 
@@ -456,6 +513,7 @@ void destroy_resources(ntt_server* s) {
     if (sl.event) (void)hipEventDestroy(sl.event);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
   }
+  for (hipStream_t w : s->wide) (void)hipStreamDestroy(w);
   for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
   if (s->base) (void)hipFree(s->base);
 }
@@ -479,6 +537,10 @@ ntt_status ntt_server_create(ntt_server** out, const ntt_server_config* config) 
   if (c.max_batch_tasks == 0) c.max_batch_tasks = 4096;
   if (c.max_batch_tasks < NTT_MAX_LIMBS || c.max_batch_tasks > (1u << 20)) return NTT_EINVAL_COUNT;
   if (c.max_queue == 0) c.max_queue = 1u << 20;
+  if (c.wide_min_log_degree == 0) c.wide_min_log_degree = kMaxOnchipLog + 1;
+  if (c.wide_max_inflight == 0) c.wide_max_inflight = 8;
+  if (c.wide_max_inflight > 1024) return NTT_EINVAL_COUNT;
+  if (c.wide_min_log_degree < 10 || c.wide_min_log_degree > NTT_MAX_LOG_DEGREE + 1) return NTT_EINVAL_COUNT;
   c.hbm_budget = align_up(c.hbm_budget);
   std::unique_ptr<ntt_server> s(new (std::nothrow) ntt_server());
   if (!s) return NTT_ENOMEM;
@@ -500,6 +562,16 @@ ntt_status ntt_server_create(ntt_server** out, const ntt_server_config* config) 
     if (e) {
       destroy_resources(s.get());
       return e;
+    }
+  }
+  if (c.mode == NTT_SERVE_BATCHED) {
+    s->wide.resize(c.streams, nullptr);
+    for (hipStream_t& w : s->wide) {
+      if (hipStreamCreateWithFlags(&w, hipStreamNonBlocking) != hipSuccess) {
+        w = nullptr;
+        destroy_resources(s.get());
+        return NTT_EDEVICE;
+      }
     }
   }
   try {

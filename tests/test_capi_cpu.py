@@ -72,6 +72,18 @@ def test_argument_validation_without_device(nt):
     assert L.eltwise_mult_mod(fake, other, other, 4, (1 << 61) + 1, 4, None) == nt.NTT_EINVAL_MODULUS
     assert L.eltwise_add_mod(fake, other, other, 4, 1, None) == nt.NTT_EINVAL_MODULUS
     assert L.eltwise_add_mod(fake, other, other, 4, 1 << 63, None) == nt.NTT_EINVAL_MODULUS
+    # fused multiply-add, subtraction, negation
+    assert L.eltwise_fma_mod(fake, None, 3, None, 4, 17, 1, None) == nt.NTT_EINVAL_POINTER
+    assert L.eltwise_fma_mod(fake, other, 3, None, 4, 17, 3, None) == nt.NTT_EINVAL_FACTOR
+    assert L.eltwise_fma_mod(fake, other, 3, None, 4, 1 << 61, 1, None) == nt.NTT_EINVAL_MODULUS
+    assert L.eltwise_fma_mod(fake, other, 3, None, 4, 1, 1, None) == nt.NTT_EINVAL_MODULUS
+    assert L.eltwise_fma_mod(fake, other, 3, None, 0, 17, 1, None) == nt.NTT_EINVAL_COUNT
+    assert L.eltwise_fma_mod(ctypes.c_void_p(0x1000000 + 8), fake, 3, None, 1024, 17, 1, None) == nt.NTT_EALIAS
+    assert L.eltwise_fma_mod(ctypes.c_void_p(0x1000000 + 8), other, 3, fake, 1024, 17, 1, None) == nt.NTT_EALIAS
+    assert L.eltwise_sub_mod(fake, other, None, 4, 17, None) == nt.NTT_EINVAL_POINTER
+    assert L.eltwise_sub_mod(fake, other, other, 4, 1 << 63, None) == nt.NTT_EINVAL_MODULUS
+    assert L.eltwise_negate_mod(None, other, 4, 17, None) == nt.NTT_EINVAL_POINTER
+    assert L.eltwise_negate_mod(ctypes.c_void_p(0x1000000 + 8), fake, 1024, 17, None) == nt.NTT_EALIAS
     # partial overlap of output and input
     shifted = ctypes.c_void_p(0x1000000 + 8)
     assert L.ntt_forward(shifted, fake, 1024, q, 1, 1, None) == nt.NTT_EALIAS
@@ -91,7 +103,8 @@ def test_server_config_validation_without_device(nt):
     lib = _raw(nt)
     h = ctypes.c_void_p()
     assert lib.ntt_server_create(None, None) == -5
-    for kw in ({"mode": 3}, {"streams": 5}, {"max_batch_tasks": 10}, {"max_batch_tasks": (1 << 20) + 1}):
+    for kw in ({"mode": 3}, {"streams": 5}, {"max_batch_tasks": 10}, {"max_batch_tasks": (1 << 20) + 1},
+               {"wide_min_log_degree": 9}, {"wide_min_log_degree": 19}):
         cfg = nt.ServerConfig(**kw)
         assert lib.ntt_server_create(ctypes.byref(h), ctypes.byref(cfg)) == -7, kw
         assert not h.value

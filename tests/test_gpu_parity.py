@@ -70,6 +70,52 @@ def test_eltwise_add_and_mult(nt, n):
     assert np.array_equal(from_dev(dc), oracle.eltwise_add(a, b, q))
 
 
+@pytest.mark.parametrize("n", [1, 3, 1024, 4097, (1 << 18) + 5])
+def test_eltwise_fma_sub_negate(nt, n):
+    """Algorithm 10 (vector-scalar multiply-add) for every input factor, with and
+    without the addend, in place; subtraction and negation (zero residues too)."""
+    for q in [2, 3, 12289, _edge(50), _edge(61), (1 << 61) - 1]:
+        for f in (1, 2, 4, 8):
+            if f * q >= (1 << 64):
+                continue
+            a = lazy_mod(unit_seed(20, n, q, f), n, q, f)
+            z = lazy_mod(unit_seed(21, n, q, f), n, q, f)
+            top = np.uint64(f * q - 1)
+            a[: max(1, n // 8)] = top
+            for y in (0, 1, q - 1, int(uniform_mod(unit_seed(22, q, f), 1, q)[0]), q + 5):
+                da, dz, dc = to_dev(a), to_dev(z), empty_dev(n)
+                nt.eltwise_fma_mod(dc, da, y, dz, n, q, f)
+                assert np.array_equal(from_dev(dc), oracle.eltwise_fma(a, y, z, q)), (q, f, y)
+                nt.eltwise_fma_mod(da, da, y, None, n, q, f)                  # in place, no addend
+                assert np.array_equal(from_dev(da), oracle.eltwise_fma(a, y, None, q)), (q, f, y)
+        a = uniform_mod(unit_seed(23, n, q), n, q)
+        b = uniform_mod(unit_seed(24, n, q), n, q)
+        a[0] = 0
+        b[-1] = a[-1]
+        da, db, dc = to_dev(a), to_dev(b), empty_dev(n)
+        nt.eltwise_sub_mod(dc, da, db, n, q)
+        assert np.array_equal(from_dev(dc), oracle.eltwise_sub(a, b, q))
+        nt.eltwise_negate_mod(da, da, n, q)
+        assert np.array_equal(from_dev(da), oracle.eltwise_negate(a, q))
+
+
+def test_eltwise_fma_rns(nt):
+    N, B = 4096 + 2, 3
+    moduli = PRIMES["serving"]["moduli"][:5]
+    moduli = [q for q in moduli if q < (1 << 61)][:3]
+    L = len(moduli)
+    scalars = [int(uniform_mod(unit_seed(25, l), 1, q)[0]) for l, q in enumerate(moduli)]
+    a = np.concatenate([lazy_mod(unit_seed(26, p, l), N, q, 4) for p in range(B) for l, q in enumerate(moduli)])
+    z = np.concatenate([lazy_mod(unit_seed(27, p, l), N, q, 4) for p in range(B) for l, q in enumerate(moduli)])
+    dc = empty_dev(a.size)
+    nt.eltwise_fma_mod_rns(dc, to_dev(a), scalars, to_dev(z), N, moduli, B, 4)
+    got = from_dev(dc)
+    for p in range(B):
+        for l, q in enumerate(moduli):
+            s = slice((p * L + l) * N, (p * L + l + 1) * N)
+            assert np.array_equal(got[s], oracle.eltwise_fma(a[s], scalars[l], z[s], q)), (p, l)
+
+
 @pytest.mark.parametrize("Q", list(range(30, 63)))
 def test_eltwise_mult_barrett_edges(nt, Q):
     """Smallest Q-bit primes (Barrett's quotient estimate is weakest just above

@@ -99,12 +99,16 @@ def test_server_mix_matches_alone_and_oracle(nt):
     assert np.array_equal(solo[0], outs[3])
 
 
-@pytest.mark.parametrize("mode", ["fifo", "per_limb", "graph"])
+@pytest.mark.parametrize("mode", ["fifo", "per_limb", "graph", "persistent_only", "all_wide"])
 def test_server_modes_agree(nt, mode):
     reqs = _mix(310, 10)
     ref, _ = _serve(nt, reqs, nt.SERVE_BATCHED)
     if mode == "graph":
         got, st = _serve(nt, reqs, nt.SERVE_BATCHED, use_graph=True, streams=3)
+    elif mode == "persistent_only":
+        got, st = _serve(nt, reqs, nt.SERVE_BATCHED, wide_min_log_degree=18)
+    elif mode == "all_wide":
+        got, st = _serve(nt, reqs, nt.SERVE_BATCHED, wide_min_log_degree=10)
     else:
         got, st = _serve(nt, reqs, nt.SERVE_FIFO if mode == "fifo" else nt.SERVE_FIFO_PER_LIMB)
     assert st["completed"] == len(reqs)
