@@ -40,6 +40,7 @@ namespace nttamd {
 // the transposed sub-tables in the low pass (-1: none).
 template <bool FWD, int LOGT, int LOGR, int LOGC, int LOGH, int MINW, int MODE, bool LASTPASS, int PTOP>
 __global__ void __launch_bounds__((1 << (LOGT + LOGH + LOGC)) >> LOGR, MINW) ntt_tile_kernel(const PassArgs a) {
+  static_assert(MINW <= 4, "the butterflies use v122..v127: keep a budget of at least 128 VGPRs");
   using K = TileNtt<FWD, LOGT, LOGR, LOGC, LOGH>;
   __shared__ u64 lds[K::LDSW];
   const u32 item = a.item0 + blockIdx.y;
@@ -54,33 +55,52 @@ __global__ void __launch_bounds__((1 << (LOGT + LOGH + LOGC)) >> LOGR, MINW) ntt
 
 typedef void (*PassKernel)(const PassArgs);
 
-// Variants of the high (strided) pass: coefficients per thread, 2^3 or 2^4.
-constexpr int kHiVariants = 2;
-static int hi_logr(int variant) { return variant == 0 ? 4 : 3; }
+// Schedule variants: (log2 coefficients per thread of the high pass, of the
+// low pass).  Fewer coefficients per thread means more waves per tile, which
+// hides more latency when the batch is small, at the price of more LDS rounds.
+// The low pass reads the plan's transposed sub-tables only with 2^kMpLogrLo
+// coefficients per thread (the layout they are built for); otherwise it reads
+// the natural table.
+constexpr int kVariants = 5;
+struct VariantShape { int hi, lo; };
+static constexpr VariantShape kVariantShape[kVariants] = {{4, 4}, {3, 4}, {2, 4}, {3, 3}, {2, 3}};
+// At most 1024 threads per workgroup: 2^(tile bits + 4 columns - log2 R).
+__host__ __device__ constexpr int hi_logr_clamped(int lt_hi, int logr) { return lt_hi + 4 - logr > 10 ? lt_hi - 6 : logr; }
+static int hi_logr(int logN, int variant) { return hi_logr_clamped(mp_logt_hi(logN), kVariantShape[variant].hi); }
+static int lo_logr(int variant) { return kVariantShape[variant].lo; }
 
-template <bool FWD, int LOGN, int MODE, bool LAST>
-static PassKernel pick_hi(int variant) {
+template <bool FWD, int LOGN, int MODE, bool LAST, int LOGR0>
+static PassKernel pick_hi_r() {
   constexpr int LT = mp_logt_hi(LOGN);
-  constexpr int MW = LT >= 9 ? 2 : 4;
-  if (variant == 0) return ntt_tile_kernel<FWD, LT, 4, 4, 0, MW, MODE, LAST, -1>;
-  return ntt_tile_kernel<FWD, LT, 3, 4, 0, MW, MODE, LAST, -1>;
+  constexpr int LOGR = hi_logr_clamped(LT, LOGR0);
+  constexpr int MW = LOGR >= 4 && LT >= 9 ? 2 : 4;   // at least 128 VGPRs: the butterflies use v122..v127
+  return ntt_tile_kernel<FWD, LT, LOGR, 4, 0, MW, MODE, LAST, -1>;
 }
 template <bool FWD, int LOGN, int MODE, bool LAST>
-static PassKernel pick_lo() {
+static PassKernel pick_hi(int variant) {
+  switch (kVariantShape[variant].hi) {
+    case 4: return pick_hi_r<FWD, LOGN, MODE, LAST, 4>();
+    case 3: return pick_hi_r<FWD, LOGN, MODE, LAST, 3>();
+    default: return pick_hi_r<FWD, LOGN, MODE, LAST, 2>();
+  }
+}
+template <bool FWD, int LOGN, int MODE, bool LAST>
+static PassKernel pick_lo(int variant) {
   constexpr int LT = mp_logt_lo(LOGN);
   constexpr int LH = 12 - LT;                          // 4096-coefficient tiles
-  return ntt_tile_kernel<FWD, LT, kMpLogrLo, 0, LH, 4, MODE, LAST, mp_perm_top(FWD, LOGN)>;
+  if (lo_logr(variant) == kMpLogrLo) return ntt_tile_kernel<FWD, LT, kMpLogrLo, 0, LH, 4, MODE, LAST, mp_perm_top(FWD, LOGN)>;
+  return ntt_tile_kernel<FWD, LT, 3, 0, LH, 4, MODE, LAST, -1>;
 }
 
 template <int LOGN>
 static PassKernel pick_pass(bool fwd, bool hi, u32 flags, int variant) {
   if (fwd) {
     if (hi) return pick_hi<true, LOGN, kOutLazy, false>(variant);           // forward: high pass first
-    if (flags & kFlagMul) return pick_lo<true, LOGN, kOutMul, true>();
-    if (flags & kFlagCanon) return pick_lo<true, LOGN, kOutCanon, true>();
-    return pick_lo<true, LOGN, kOutLazy, true>();
+    if (flags & kFlagMul) return pick_lo<true, LOGN, kOutMul, true>(variant);
+    if (flags & kFlagCanon) return pick_lo<true, LOGN, kOutCanon, true>(variant);
+    return pick_lo<true, LOGN, kOutLazy, true>(variant);
   }
-  if (!hi) return pick_lo<false, LOGN, kOutLazy, false>();                   // inverse: low pass first
+  if (!hi) return pick_lo<false, LOGN, kOutLazy, false>(variant);            // inverse: low pass first
   if (flags & kFlagAcc) return pick_hi<false, LOGN, kOutAcc, true>(variant);
   if (flags & kFlagCanon) return pick_hi<false, LOGN, kOutCanon, true>(variant);
   return pick_hi<false, LOGN, kOutLazy, true>(variant);
@@ -98,7 +118,7 @@ static PassKernel pick_pass_n(int logN, bool fwd, bool hi, u32 flags, int varian
 // Number of passes the schedule for 2^logN uses (1 = the whole transform on chip).
 int pass_count(int logN) { return logN <= kMaxOnchipLog ? 1 : 2; }
 
-// High-pass variant per (direction, logN, batch size); set by the autotuner.
+// Schedule variant per (direction, logN, batch size); set by the autotuner.
 static int g_hi_variant[2][NTT_MAX_LOG_DEGREE + 1][2];
 static int batch_bucket(uint64_t items) { return items <= 64 ? 0 : 1; }
 
@@ -106,7 +126,7 @@ void set_hi_variant(bool fwd, int logN, uint64_t items, int variant) {
   g_hi_variant[fwd ? 1 : 0][logN][batch_bucket(items)] = variant;
 }
 int get_hi_variant(bool fwd, int logN, uint64_t items) { return g_hi_variant[fwd ? 1 : 0][logN][batch_bucket(items)]; }
-int hi_variant_count() { return kHiVariants; }
+int hi_variant_count() { return kVariants; }
 
 static ntt_status launch_passes(const NttLaunch& l, bool fwd, int force_variant) {
   const ntt_plan* p0 = l.plans[0];
@@ -148,12 +168,12 @@ static ntt_status launch_passes(const NttLaunch& l, bool fwd, int force_variant)
     uint64_t tiles;
     if (hi) {
       a.b0 = (u32)lt_lo;
-      const int logr = hi_logr(variant);
+      const int logr = hi_logr(logN, variant);
       nt = 1 << (lt_hi + 4 - logr);
       tiles = ((1ull << lt_lo) >> 4) * (1ull << (logN - lt_lo - lt_hi));
     } else {
       a.b0 = 0;
-      nt = 1 << (12 - kMpLogrLo);
+      nt = 1 << (12 - lo_logr(variant));
       tiles = 1ull << (logN - 12);
     }
     for (uint64_t it0 = 0; it0 < items; it0 += kMaxY) {

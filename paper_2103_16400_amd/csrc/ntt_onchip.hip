@@ -32,6 +32,7 @@ namespace nttamd {
 // MINW: waves per SIMD the register allocation must allow (occupancy target).
 template <bool FWD, int LOGN, int LOGR, bool SPLIT, int MINW, int MODE>
 __global__ void __launch_bounds__(1 << (LOGN - LOGR), MINW) ntt_onchip_kernel(const PassArgs a) {
+  static_assert(MINW <= 4, "the butterflies use v122..v127: keep a budget of at least 128 VGPRs");
   using K = OnChip<FWD, LOGN, LOGR, SPLIT>;
   __shared__ typename K::W lds[K::LDSW];
   const u32 item = a.item0 + blockIdx.x;

@@ -264,6 +264,70 @@ def _rns_inputs(tag, N, moduli, B, f=1):
     return out
 
 
+def _variant_count(nt, N):
+    v = 0
+    while True:
+        try:
+            nt.set_variant(N, 2, True, v)
+        except nt.NttError:
+            return v
+        v += 1
+
+
+@pytest.mark.parametrize("logN", [15, 16, 17])
+def test_two_pass_schedule_variants(nt, logN):
+    """Every schedule variant of the two-pass kernels (threads per tile of each
+    pass) gives the oracle's words: forward lazy (equal to the Harvey model),
+    canonical and fused multiply; inverse canonical and fused accumulate."""
+    N = 1 << logN
+    moduli = PRIMES["serving"]["moduli"][7:9]
+    L = len(moduli)
+    psis = [oracle.min_root(N, q) for q in moduli]
+    a = _rns_inputs(80, N, moduli, 1, 4)
+    m = _rns_inputs(81, N, moduli, 1, 4)
+    acc0 = _rns_inputs(82, N, moduli, 1, 1)
+    A = _rns_inputs(83, N, moduli, 1, 2)
+    idx = _sample_idx(N, 84, 10)
+    ref_fwd = [oracle.ntt_forward_at(a[l * N:(l + 1) * N], idx, q, psis[l]) for l, q in enumerate(moduli)]
+    harvey0 = oracle.harvey_forward(a[:N], moduli[0], psis[0], 4)
+    ref_inv = [oracle.ntt_inverse_at(A[l * N:(l + 1) * N], idx, q, psis[l]) for l, q in enumerate(moduli)]
+    nv = _variant_count(nt, N)
+    assert nv >= 5
+    ws = empty_dev(L * N)
+    try:
+        for v in range(nv):
+            nt.set_variant(N, L, True, v)
+            nt.set_variant(N, L, False, v)
+            da, dout = to_dev(a), empty_dev(L * N)
+            nt.ntt_forward_rns(dout, da, N, moduli, 1, 4, 4)
+            lazy = from_dev(dout)
+            assert np.array_equal(lazy[:N], harvey0), v
+            nt.ntt_forward_rns(dout, da, N, moduli, 1, 4, 1)
+            canon = from_dev(dout)
+            for l, q in enumerate(moduli):
+                s = slice(l * N, (l + 1) * N)
+                assert np.array_equal(canon[s][idx], ref_fwd[l]), (v, l)
+                assert np.array_equal(canon[s], lazy[s] % np.uint64(q)), (v, l)
+            dm = to_dev(m)
+            nt.ntt_forward_mul_rns(dm, da, dm, N, moduli, 1, 4, ws)
+            prod = from_dev(dm)
+            for l, q in enumerate(moduli):
+                s = slice(l * N, (l + 1) * N)
+                assert np.array_equal(prod[s], oracle.eltwise_mult(canon[s], m[s], q)), (v, l)
+            dA = to_dev(A)
+            nt.ntt_inverse_rns(dout, dA, N, moduli, 1, 2, 1)
+            inv = from_dev(dout)
+            for l, q in enumerate(moduli):
+                assert np.array_equal(inv[l * N:(l + 1) * N][idx], ref_inv[l]), (v, l)
+            dacc = to_dev(acc0)
+            nt.ntt_inverse_acc_rns(dacc, dA, N, moduli, 1, 2, ws)
+            assert np.array_equal(from_dev(dacc), np.concatenate(
+                [oracle.eltwise_add(acc0[l * N:(l + 1) * N], inv[l * N:(l + 1) * N], q) for l, q in enumerate(moduli)])), v
+    finally:
+        nt.set_variant(N, L, True, 0)
+        nt.set_variant(N, L, False, 0)
+
+
 @pytest.mark.parametrize("key,B", [("rns_16384", 2), ("large_65536", 1)])
 def test_rns_forward_inverse(nt, key, B):
     N = PRIMES[key]["N"]
