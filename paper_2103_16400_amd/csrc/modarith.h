@@ -105,8 +105,10 @@ __device__ __forceinline__ void harvey_inv_last_c(u64& x0, u64& x1, u64 ni, u64 
 // outputs in [0, 4q):  X0 <- X0 + W X1,  X1 <- X0 - W X1  (mod q).
 // nq = 2^64 - q, nq2 = 2^64 - 2q.  Only P = v[124:125] and T = v[126:127]
 // are used: once Q has served its low-word product, its pair holds the 32-bit
-// cross products.  The outputs are written only after every operand has been
-// read, so they may reuse the input registers.
+// cross products.  X1 is written last, so it may reuse an input register; X0
+// is written before the last read of 2q and is therefore early-clobber (an
+// "s" operand can end up in a VGPR where the compiler cannot keep it uniform,
+// e.g. inside a non-inlined function).
 __device__ __forceinline__ void harvey_fwd(u64& x0, u64& x1, u64 w, u64 wp, u64 q2, u64 nq, u64 nq2) {
   u64 k, c, j, b, y0, y1;
   asm volatile("v_cmp_le_u64 %[k], %[q2], %[x0]\n\t"                 // x0 >= 2q
@@ -134,7 +136,7 @@ __device__ __forceinline__ void harvey_fwd(u64& x0, u64& x1, u64 w, u64 wp, u64 
       "s_nop 1\n\t"
       "v_subb_co_u32 v125, %[b], v125, v127, %[b]\n\t"
       "v_lshl_add_u64 %[y1], v[124:125], 0, 0"                       // X1 = A + 2q - T
-      : [y0] "=v"(y0), [y1] "=v"(y1), [k] "=&s"(k), [c] "=&s"(c), [j] "=&s"(j), [b] "=&s"(b)
+      : [y0] "=&v"(y0), [y1] "=v"(y1), [k] "=&s"(k), [c] "=&s"(c), [j] "=&s"(j), [b] "=&s"(b)
       : [x0] "v"(x0), [x0l] "v"(lo32(x0)), [x0h] "v"(hi32(x0)), [x1l] "v"(lo32(x1)), [x1h] "v"(hi32(x1)),
         [wl] "v"(lo32(w)), [wh] "v"(hi32(w)), [pl] "v"(lo32(wp)), [ph] "v"(hi32(wp)), [q2] "s"(q2), [nq2] "s"(nq2),
         [nql] "s"(lo32(nq)), [nqh] "s"(hi32(nq))

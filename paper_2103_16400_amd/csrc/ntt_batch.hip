@@ -10,9 +10,6 @@
 //   * N >= 2^15: both passes of the two-pass transform (ntt_tile.h), one
 //     4096-coefficient tile at a time; the intermediate stays in the limb's
 //     output buffer and the workgroup barrier orders the passes.
-// The butterflies here are the plain C++ ones: the hand-scheduled statements
-// give wrong words inside these non-inlined task functions (open issue), so
-// this kernel keeps the arithmetic the compiler schedules.
 // Operations: forward (lazy [0, 4q) or canonical), inverse (lazy [0, 2q) or
 // canonical) and the negacyclic product out = a * b of the Section 4 listing
 // (forward(a), forward(b) fused with the multiply, inverse).  The task list
@@ -69,7 +66,7 @@ template <bool FWD, int LOGN, int MODE>
 __device__ __attribute__((noinline)) void task_onchip(const u64* plan, const u64* in, u64* out, const u64* mul, u32* lds,
                                             bool nt) {
   const PlanView pv = load_plan(plan, FWD, 1ull << LOGN);
-  onchip_body<FWD, LOGN, LOGN - 9, true, MODE, false>(pv, in, out, mul, lds, nt);
+  onchip_body<FWD, LOGN, LOGN - 9, true, MODE, true>(pv, in, out, mul, lds, nt);
 }
 
 // Both passes of a two-pass transform by one workgroup (512 threads, tiles of
@@ -93,11 +90,11 @@ __device__ __attribute__((noinline)) void task_twopass(const u64* plan, const u6
 #pragma unroll 1
     for (u32 tile = 0; tile < (u32)TILES; ++tile) {
       if (hi) {
-        if (last) tile_body<FWD, LT_HI, 3, LC_HI, 0, MODE, true, -1, false>(pv, LOGN, LT_LO, tile, src, dst, mul, lds, false);
-        else tile_body<FWD, LT_HI, 3, LC_HI, 0, kOutLazy, false, -1, false>(pv, LOGN, LT_LO, tile, src, dst, mul, lds, nt);
+        if (last) tile_body<FWD, LT_HI, 3, LC_HI, 0, MODE, true, -1, true>(pv, LOGN, LT_LO, tile, src, dst, mul, lds, false);
+        else tile_body<FWD, LT_HI, 3, LC_HI, 0, kOutLazy, false, -1, true>(pv, LOGN, LT_LO, tile, src, dst, mul, lds, nt);
       } else {
-        if (last) tile_body<FWD, LT_LO, 3, 0, LH_LO, MODE, true, -1, false>(pv, LOGN, 0, tile, src, dst, mul, lds, false);
-        else tile_body<FWD, LT_LO, 3, 0, LH_LO, kOutLazy, false, -1, false>(pv, LOGN, 0, tile, src, dst, mul, lds, nt);
+        if (last) tile_body<FWD, LT_LO, 3, 0, LH_LO, MODE, true, -1, true>(pv, LOGN, 0, tile, src, dst, mul, lds, false);
+        else tile_body<FWD, LT_LO, 3, 0, LH_LO, kOutLazy, false, -1, true>(pv, LOGN, 0, tile, src, dst, mul, lds, nt);
       }
       __syncthreads();
     }
