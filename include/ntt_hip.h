@@ -237,6 +237,17 @@ ntt_status ntt_inverse_acc_rns(uint64_t* acc, const uint64_t* operand, uint64_t 
 ntt_status poly_mul_acc_rns(uint64_t* acc, const uint64_t* a, const uint64_t* b, uint64_t N,
                             const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
                             uint64_t* workspace, ntt_stream_t stream);
+/* acc += a * b with a given in NTT form: a_ntt is the forward transform of a
+ * (lazy output, values in [0, 4q), e.g. from ntt_forward_rns with
+ * output_mod_factor 4), b in coefficient form in [0, q); acc canonical.  For
+ * N <= 2^14 this is one launch that keeps each limb on chip (forward of b,
+ * multiply, inverse, accumulate; workspace may be NULL); above, the forward
+ * of b fused with the multiply and the inverse fused with the accumulate,
+ * with a workspace of 2 * num_polys * num_limbs * N words.  acc must not
+ * overlap a_ntt or b. */
+ntt_status poly_mul_acc_ntt_rns(uint64_t* acc, const uint64_t* a_ntt, const uint64_t* b, uint64_t N,
+                                const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys, uint64_t* workspace,
+                                ntt_stream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Batches of limb tasks with uneven ring degrees in one persistent launch.

@@ -56,6 +56,7 @@ _SIGS = {
     "ntt_batch_run_graph": (_ST, [_P, _P, ctypes.c_size_t, _P]),
     "ntt_batch_autotune": (_ST, [_P, _P, ctypes.c_size_t, _P, ctypes.POINTER(ctypes.c_int)]),
     "eltwise_fma_mod": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _P]),
+    "poly_mul_acc_ntt_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P, _P]),
     "eltwise_fma_mod_rns": (_ST, [_P, _P, _P, _P, _U64, _P, _U64, _U64, _U64, _P]),
     "eltwise_sub_mod": (_ST, [_P, _P, _P, _U64, _U64, _P]),
     "eltwise_negate_mod": (_ST, [_P, _P, _U64, _U64, _P]),
@@ -310,6 +311,13 @@ class Batch:
             items, count = self.make_items(items)
         fn = _lib.ntt_batch_run_graph if graph else _lib.ntt_batch_run
         _check(fn(self._h, items, count, _stream(stream)), "ntt_batch_run_graph" if graph else "ntt_batch_run")
+
+
+def poly_mul_acc_ntt_rns(acc, a_ntt, b, N, moduli, num_polys, workspace=None, stream=None):
+    """acc += a * b with a given as its forward NTT (lazy outputs allowed)."""
+    m, L = _moduli(moduli)
+    _check(_lib.poly_mul_acc_ntt_rns(_ptr(acc), _ptr(a_ntt), _ptr(b), N, m, L, num_polys, _ptr(workspace),
+                                     _stream(stream)), "poly_mul_acc_ntt_rns")
 
 
 def eltwise_fma_mod(result, arg1, arg2, arg3, n, modulus, input_mod_factor=1, stream=None):

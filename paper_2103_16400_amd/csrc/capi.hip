@@ -77,6 +77,17 @@ ntt_status ntt_rns(bool fwd, uint64_t* result, const uint64_t* operand, const ui
   return fwd ? launch_forward(l) : launch_inverse(l);
 }
 
+// Second half of a fused product for N <= 2^14 (one launch): out = InvNTT(NTT(b) (.) m),
+// or out += it; m = NTT(a), lazy.
+ntt_status product_rns(bool acc, uint64_t* out, const uint64_t* b, const uint64_t* m, uint64_t N,
+                       const uint64_t* moduli, uint64_t L, uint64_t B, ntt_stream_t stream) {
+  std::vector<const ntt_plan*> plans;
+  ntt_status st = rns_plans(N, moduli, L, plans);
+  if (st) return st;
+  NttLaunch l{out, b, m, nullptr, plans.data(), (uint32_t)L, B, 1, 1, (hipStream_t)stream};
+  return launch_product(l, acc);
+}
+
 ntt_status elt_rns(bool mult, uint64_t* result, const uint64_t* a, const uint64_t* b, uint64_t N,
                    const uint64_t* moduli, uint64_t L, uint64_t B, uint64_t in_f, ntt_stream_t stream) {
   if (!result || !a || !b || !moduli) return NTT_EINVAL_POINTER;
@@ -335,6 +346,8 @@ ntt_status poly_mul_rns(uint64_t* result, const uint64_t* a, const uint64_t* b, 
   // result <- NTT(a) in [0, 4q)
   st = ntt_rns(true, result, a, nullptr, nullptr, N, moduli, num_limbs, num_polys, 1, 4, stream);
   if (st) return st;
+  // on chip: result <- InvNTT(NTT(b) (.) result) in one launch
+  if (one_pass) return product_rns(false, result, b, result, N, moduli, num_limbs, num_polys, stream);
   // result <- NTT(b) (.) result, canonical (last pass of forward(b) fused with the multiply, factor 4)
   st = ntt_rns(true, result, b, result, one_pass ? nullptr : workspace, N, moduli, num_limbs, num_polys, 1, 4,
                stream);
@@ -362,11 +375,37 @@ ntt_status poly_mul_acc_rns(uint64_t* acc, const uint64_t* a, const uint64_t* b,
   // prod <- NTT(a), lazy
   st = ntt_rns(true, prod, a, nullptr, nullptr, N, moduli, num_limbs, num_polys, 1, 4, stream);
   if (st) return st;
+  // on chip: acc <- acc + InvNTT(NTT(b) (.) prod) in one launch
+  if (one_pass) return product_rns(true, acc, b, prod, N, moduli, num_limbs, num_polys, stream);
   // prod <- NTT(b) (.) prod, canonical
   st = ntt_rns(true, prod, b, prod, mid, N, moduli, num_limbs, num_polys, 1, 4, stream);
   if (st) return st;
   // acc <- acc + InvNTT(prod); the inverse's intermediate passes run in place on prod
   return ntt_rns(false, acc, prod, acc, one_pass ? nullptr : prod, N, moduli, num_limbs, num_polys, 1, 1, stream);
+}
+
+ntt_status poly_mul_acc_ntt_rns(uint64_t* acc, const uint64_t* a_ntt, const uint64_t* b, uint64_t N,
+                                const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys, uint64_t* workspace,
+                                ntt_stream_t stream) {
+  if (!acc || !a_ntt || !b) return NTT_EINVAL_POINTER;
+  if (num_limbs == 0 || num_polys == 0) return NTT_EINVAL_COUNT;
+  ntt_status st = validate_degree(N);
+  if (st) return st;
+  if (num_polys > (1ull << 39) / (num_limbs * N)) return NTT_EINVAL_COUNT;
+  const size_t bytes = (size_t)(num_polys * num_limbs * N * sizeof(uint64_t));
+  if (overlaps(acc, bytes, a_ntt, bytes) || overlaps(acc, bytes, b, bytes)) return NTT_EALIAS;
+  if (is_one_pass(N)) return product_rns(true, acc, b, a_ntt, N, moduli, num_limbs, num_polys, stream);
+  if (!workspace) return NTT_EINVAL_POINTER;
+  const size_t wbytes = 2 * bytes;
+  if (overlaps(workspace, wbytes, acc, bytes) || overlaps(workspace, wbytes, a_ntt, bytes) ||
+      overlaps(workspace, wbytes, b, bytes))
+    return NTT_EALIAS;
+  uint64_t* prod = workspace;
+  uint64_t* mid = workspace + bytes / sizeof(uint64_t);
+  // prod <- NTT(b) (.) a_ntt, canonical; then acc <- acc + InvNTT(prod)
+  st = ntt_rns(true, prod, b, a_ntt, mid, N, moduli, num_limbs, num_polys, 1, 4, stream);
+  if (st) return st;
+  return ntt_rns(false, acc, prod, acc, prod, N, moduli, num_limbs, num_polys, 1, 1, stream);
 }
 
 ntt_status ntt_autotune(uint64_t N, const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,

@@ -117,6 +117,9 @@ struct NttLaunch {
   hipStream_t stream;
 };
 ntt_status launch_forward(const NttLaunch& l);
+// N <= 2^14: out = InvNTT(NTT(in) (.) mul_into) canonical, or out += that (acc);
+// mul_into is NTT(a) with the forward's lazy output range; out may equal mul_into.
+ntt_status launch_product(const NttLaunch& l, bool acc);
 int pass_count(int logN);
 // autotuner hooks (ntt_kernels.hip): variants of the high pass of two-pass transforms
 ntt_status launch_variant(const NttLaunch& l, bool fwd, int variant);

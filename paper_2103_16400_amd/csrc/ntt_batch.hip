@@ -101,6 +101,26 @@ __device__ __attribute__((noinline)) void task_twopass(const u64* plan, const u6
   }
 }
 
+// Second half of a product on chip: out = InvNTT(NTT(b) (.) out), canonical.
+template <int LOGN>
+__device__ __attribute__((noinline)) void task_product_onchip(const u64* plan, const u64* b, u64* out, u32* lds) {
+  const PlanView pf = load_plan(plan, true, 1ull << LOGN);
+  const PlanView pi = load_plan(plan, false, 1ull << LOGN);
+  onchip_product_body<LOGN, LOGN - 9, true, kOutCanon, true>(pf, pi, b, out, out, lds, true);
+}
+
+__device__ __forceinline__ void run_product_onchip(u32 logN, const u64* plan, const u64* b, u64* out, void* lds) {
+  u32* l32 = reinterpret_cast<u32*>(lds);
+  switch (logN) {
+    case 10: task_product_onchip<10>(plan, b, out, l32); break;
+    case 11: task_product_onchip<11>(plan, b, out, l32); break;
+    case 12: task_product_onchip<12>(plan, b, out, l32); break;
+    case 13: task_product_onchip<13>(plan, b, out, l32); break;
+    case 14: task_product_onchip<14>(plan, b, out, l32); break;
+    default: break;
+  }
+}
+
 template <bool FWD, int MODE>
 __device__ __forceinline__ void run_transform(u32 logN, const u64* plan, const u64* in, u64* mid, u64* out,
                                               const u64* mul, void* lds, bool nt) {
@@ -145,6 +165,10 @@ __global__ void __launch_bounds__(kBatchThreads, 4)
         // out <- NTT(a) lazy; out <- NTT(b) (.) out (first pass of NTT(b) in tmp); out <- InvNTT(out)
         run_transform<true, kOutLazy>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true);
         __syncthreads();
+        if (tk.logN <= (u32)kMaxOnchipLog) {        // the rest on chip, in one step
+          run_product_onchip(tk.logN, tk.plan, tk.in2, tk.out, lds);
+          break;
+        }
         run_transform<true, kOutMul>(tk.logN, tk.plan, tk.in2, tk.tmp, tk.out, tk.out, lds, true);
         __syncthreads();
         run_transform<false, kOutCanon>(tk.logN, tk.plan, tk.out, tk.out, tk.out, nullptr, lds, false);

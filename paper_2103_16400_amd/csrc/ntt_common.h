@@ -109,5 +109,8 @@ __device__ __forceinline__ u64 finish(u64 v, u64 idx, const PassArgs& a, const P
 }
 
 ntt_status launch_onchip(const PassArgs& base_args, uint64_t items, bool fwd, hipStream_t stream);
+// Fused product per limb for N <= 2^14: in = b, mul = NTT(a) lazy, out =
+// canonical product (acc false) or accumulator += product (acc true).
+ntt_status launch_onchip_product(const PassArgs& base_args, uint64_t items, bool acc, hipStream_t stream);
 
 }  // namespace nttamd

@@ -186,6 +186,22 @@ static ntt_status launch_passes(const NttLaunch& l, bool fwd, int force_variant)
   return NTT_OK;
 }
 
+// Fused product per limb (N <= 2^14): in = b, mul_into = NTT(a) lazy, out =
+// canonical product or accumulator.
+ntt_status launch_product(const NttLaunch& l, bool acc) {
+  const int logN = l.plans[0]->logN;
+  if (logN > kMaxOnchipLog) return NTT_EINVAL_DEGREE;
+  if (l.num_limbs == 0 || l.num_limbs > (uint32_t)kMaxPlansPerLaunch) return NTT_EINVAL_COUNT;
+  PassArgs a{};
+  for (uint32_t i = 0; i < l.num_limbs; ++i) a.plan[i] = l.plans[i]->dev;
+  a.num_limbs = l.num_limbs;
+  a.logN = (u32)logN;
+  a.in = l.in;
+  a.out = l.out;
+  a.mul = l.mul_into;
+  return launch_onchip_product(a, l.num_polys * l.num_limbs, acc, l.stream);
+}
+
 ntt_status launch_forward(const NttLaunch& l) { return launch_passes(l, true, -1); }
 ntt_status launch_inverse(const NttLaunch& l) { return launch_passes(l, false, -1); }
 ntt_status launch_variant(const NttLaunch& l, bool fwd, int variant) { return launch_passes(l, fwd, variant); }

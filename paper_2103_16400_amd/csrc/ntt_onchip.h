@@ -164,6 +164,14 @@ struct OnChip {
   }
 };
 
+// A copy of v the compiler cannot see through: index arithmetic for the output
+// phase is then recomputed instead of being kept (and spilled) from the input
+// phase.
+__device__ __forceinline__ u32 opaque(u32 v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // Transforms one limb: reads `in` (N coefficients), writes `out`; the output
 // step applies MODE with the per-item multiplier / accumulator `mul`.
 template <bool FWD, int LOGN, int LOGR, bool SPLIT, int MODE, bool HAND = true>
@@ -203,6 +211,67 @@ __device__ __forceinline__ void onchip_body(const PlanView& pv, const u64* in, u
   for (int j = 0; j < R; ++j) {
     const u32 i = direct_out ? K::template rho<RL>(t, j) : (u32)j * NT + t;
     out[i] = finish_item<FWD, MODE>(x[j], mul, i, pv);
+    if ((j & 7) == 7) stage_fence();
+  }
+}
+
+// The negacyclic product of one limb kept on chip (the product listing of
+// Section 4, fused): forward(b) lazy in [0, 4q), element-wise multiply by m =
+// NTT(a) (lazy, [0, 4q)) with Algorithm 8, inverse, then the output step MODE
+// (canonical, or accumulated into out).  With 2^LOGR coefficients per thread
+// the forward's last round and the inverse's first round both give thread t
+// the coefficients t R .. t R + R - 1, so the product and the inverse start
+// in registers.  Every thread reads its multipliers before the inverse's
+// first LDS barrier, so out may equal m.
+template <int LOGN, int LOGR, bool SPLIT, int MODE, bool HAND = true>
+__device__ __forceinline__ void onchip_product_body(const PlanView& pf, const PlanView& pi, const u64* b,
+                                                    const u64* m, u64* out,
+                                                    typename OnChip<true, LOGN, LOGR, SPLIT, HAND>::W* lds,
+                                                    bool nt_load) {
+  using KF = OnChip<true, LOGN, LOGR, SPLIT, HAND>;
+  using KI = OnChip<false, LOGN, LOGR, SPLIT, HAND>;
+  constexpr int R = KF::R;
+  constexpr int NT = KF::NT;
+  constexpr int RLF = KF::G::NR - 1;
+  constexpr int RLI = KI::G::NR - 1;
+  static_assert(KF::G::lo(RLF) == 0 && KI::G::lo(0) == 0, "forward output and inverse input layouts must coincide");
+  constexpr bool direct_in = KF::G::lo(0) >= 4 || LOGN - LOGR < 4;
+  constexpr bool direct_out = KI::G::lo(RLI) >= 4 || LOGN - LOGR < 4;
+  const u32 t = threadIdx.x;
+  u64 x[R];
+  if constexpr (direct_in) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const u64* p = &b[KF::template rho<0>(t, j)];
+      x[j] = nt_load ? __builtin_nontemporal_load(p) : *p;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const u64* p = &b[(u32)j * NT + t];
+      x[j] = nt_load ? __builtin_nontemporal_load(p) : *p;
+    }
+    const u32 bi = KF::template row_base<0>(t);
+    KF::shuffle(lds, x, [&](int j) { return KF::lin_row(t, j); }, [&](int j) { return bi + KF::template row_off<0>(j); });
+  }
+  KF::template run<0>(lds, x, t, pf);
+  const u64* mt = m + ((u64)opaque(t) << LOGR);  // KF::rho<RLF>(t, j) = t R + j
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    x[j] = barrett_mulmod<4>(x[j], mt[j], pf.q, pf.q2, pf.bk, pf.qbits);
+    if ((j & 7) == 7) stage_fence();
+  }
+  __syncthreads();                                // the forward's last LDS reads precede the inverse's writes
+  KI::template run<0>(lds, x, t, pi);
+  const u32 to = opaque(t);
+  if constexpr (!direct_out) {
+    const u32 bo = KI::template row_base<RLI>(to);
+    KI::shuffle(lds, x, [&](int j) { return bo + KI::template row_off<RLI>(j); }, [&](int j) { return KI::lin_row(to, j); });
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const u32 i = direct_out ? KI::template rho<RLI>(to, j) : (u32)j * NT + to;
+    out[i] = finish_item<false, MODE>(x[j], out, i, pi);
     if ((j & 7) == 7) stage_fence();
   }
 }

@@ -405,6 +405,39 @@ def test_poly_mul_rns(nt, logN, L, B):
     assert np.array_equal(from_dev(da), out)
 
 
+@pytest.mark.parametrize("logN,L,B", [(1, 1, 2), (6, 2, 2), (10, 3, 2), (12, 4, 1), (13, 2, 2), (14, 8, 2),
+                                      (15, 2, 1), (17, 1, 1)])
+def test_poly_mul_acc_ntt(nt, logN, L, B):
+    """acc += a * b with a in NTT form: the on-chip fused product (N <= 2^14) and
+    the two-launch form above agree with the schoolbook product plus acc."""
+    N = 1 << logN
+    moduli = PRIMES["serving"]["moduli"][3:3 + L]
+    a = _rns_inputs(90, N, moduli, B)
+    b = _rns_inputs(91, N, moduli, B)
+    acc0 = _rns_inputs(92, N, moduli, B)
+    a_ntt = empty_dev(a.size)
+    nt.ntt_forward_rns(a_ntt, to_dev(a), N, moduli, B, 1, 4)
+    dacc = to_dev(acc0)
+    ws = empty_dev(2 * a.size) if N > (1 << 14) else None
+    nt.poly_mul_acc_ntt_rns(dacc, a_ntt, to_dev(b), N, moduli, B, ws)
+    got = from_dev(dacc)
+    idx = _sample_idx(N, 93, 12)
+    for p in range(B):
+        for l, q in enumerate(moduli):
+            s = slice((p * L + l) * N, (p * L + l + 1) * N)
+            if N <= 2048:
+                ref = oracle.eltwise_add(acc0[s], oracle.negacyclic_mul(a[s], b[s], q), q)
+                assert np.array_equal(got[s], ref), (p, l)
+            else:
+                ref = oracle.eltwise_add(acc0[s][idx], oracle.negacyclic_mul_at(a[s], b[s], idx, q), q)
+                assert np.array_equal(got[s][idx], ref), (p, l)
+    # and the same words as the three-step form through the public entry points
+    dacc2 = to_dev(acc0)
+    ws2 = empty_dev(2 * a.size)
+    nt.poly_mul_acc_rns(dacc2, to_dev(a), to_dev(b), N, moduli, B, ws2)
+    assert np.array_equal(from_dev(dacc2), got)
+
+
 @pytest.mark.parametrize("logN,L,B", [(3, 2, 2), (11, 3, 2), (14, 8, 1), (15, 2, 1), (17, 1, 1)])
 def test_fused_forward_mul_and_inverse_acc(nt, logN, L, B):
     N = 1 << logN
