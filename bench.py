@@ -13,9 +13,11 @@ run inside the same timed step).  Inputs are seeded synthetic uniform
 coefficients, resident in device memory before timing starts.
 
 Also reported, on the same JSON line:
-  roofline      the forward transform of one operand batch (the dominant kernel
-                sequence), algorithmic bytes / average duration (HIP events on the
-                launch stream) against 8 TB/s;
+  roofline      the dominant kernel of the step (the fused per-limb product:
+                forward(b), multiply, inverse, accumulate), algorithmic bytes /
+                average duration (HIP events on the launch stream) against 8 TB/s,
+                with the VALU issue share beside it; roofline_fwd gives the same
+                for the forward transform of the other operand;
   cpu_baseline  the CPU oracle (O(N^2) direct forward transform) on a bounded
                 sample, timed on this host's cores.
 """
@@ -32,28 +34,49 @@ import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes of the dominant kernel (forward transform, N = 2^14, 4096 limbs, one launch) from two
-# rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean of
-# 3 dispatches), each scaled by the same counter's reading for a plain 1 GiB device copy (FETCH_SIZE
-# read 524300 KiB for 1048576 KiB copied: x2.0; WRITE_SIZE read 1048576 KiB: x1.0).  Valid only for
-# the kernel sources they were taken with, identified by the SHA-256 of these files.
-TRAFFIC_FWD_N16384 = {
-    "fetch_kib": 275674.9, "fetch_scale": 2.0, "write_kib": 524288.2, "write_scale": 1.0,
-    "sources": ["ntt_onchip.hip", "ntt_onchip.h", "ntt_common.h", "modarith.h"],
-    "sha256": "b36ec01057fa906d2188a47427f1000dbad5b5e597423de5626d9754ef0ce7a0",
+# Per-launch hardware counters of the two kernels of the step (N = 2^14, 4096 limbs), from
+# rocprofv3 --pmc runs of this benchmark, mean over the dispatches of each kernel:
+#   fetch_kib, write_kib   FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each later scaled by the
+#                          same counter's reading for a plain 1 GiB device copy (FETCH_SIZE read
+#                          524300 KiB for 1048576 KiB copied: x2.0; WRITE_SIZE 1048576 KiB: x1.0);
+#   valu_insts             SQ_INSTS_VALU (wave-level VALU instructions per dispatch).
+# Valid only for the kernel sources they were taken with, identified by the SHA-256 of these files.
+COUNTERS_N16384 = {
+    "sources": ["ntt_onchip.hip", "ntt_onchip.h", "ntt_common.h", "modarith.h", "internal.h"],
+    "sha256": "fe31532ffb9e13795880496352b74b6fabf86d5828c884fde37442a286acfa40",
+    "fetch_scale": 2.0, "write_scale": 1.0,
+    "product": {"fetch_kib": 832395.2, "write_kib": 540672.0, "valu_insts": 427556864},
+    "forward": {"fetch_kib": 275263.2, "write_kib": 524288.1, "valu_insts": 175996928},
 }
 
+# VALU issue capacity: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at 2.4 GHz
+VALU_WAVE_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
 
-def measured_traffic(t):
-    """HBM bytes per launch from the stored counters, or None once the kernel sources changed."""
+
+def counters_valid(c):
+    """True while the kernel sources are the ones the stored counters were taken with."""
     import hashlib
     h = hashlib.sha256()
-    for f in t["sources"]:
+    for f in c["sources"]:
         with open(os.path.join(ROOT, "paper_2103_16400_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != t["sha256"]:
+    return h.hexdigest() == c["sha256"]
+
+
+def measured_traffic(c, kernel):
+    """HBM bytes per launch from the stored counters, or None once the kernel sources changed."""
+    k = c[kernel]
+    if not counters_valid(c) or k["fetch_kib"] is None:
         return None
-    return int((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024)
+    return int((k["fetch_kib"] * c["fetch_scale"] + k["write_kib"] * c["write_scale"]) * 1024)
+
+
+def valu_share(c, kernel, avg_ms):
+    """Fraction of the chip's VALU issue slots the kernel's instructions fill over its duration."""
+    k = c[kernel]
+    if not counters_valid(c) or k["valu_insts"] is None:
+        return None
+    return round(k["valu_insts"] / (avg_ms * 1e-3 * VALU_WAVE_INSTS_PER_S), 4)
 
 
 def load_primes():
@@ -374,17 +397,15 @@ def main():
 
     def step(record):
         if record:
-            es = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            es = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
             es[0].record(stream)
         nt.ntt_forward_rns(c, a, N, moduli, B, 1, 4, stream=stream)             # c = NTT(a), lazy [0, 4q)
         if record:
             es[1].record(stream)
-        if record:
-            es[2].record(stream)
         # acc += InvNTT(NTT(b) (.) c): one launch, each limb kept on chip
         nt.poly_mul_acc_ntt_rns(acc, c, b, N, moduli, B, ws, stream=stream)
         if record:
-            es[3].record(stream)
+            es[2].record(stream)
             ev.append(es)
 
     for _ in range(args.warmup):
@@ -397,13 +418,24 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
     fwd_ms = float(np.mean([es[0].elapsed_time(es[1]) for es in ev]))
-    prod_ms = float(np.mean([es[2].elapsed_time(es[3]) for es in ev]))
+    prod_ms = float(np.mean([es[1].elapsed_time(es[2]) for es in ev]))
 
     limbs = B * L
     fwd_per_step = 2 * limbs
     value = fwd_per_step / (wall / args.steps)
-    alg_bytes = 16 * N * limbs + 16 * N * L        # coefficients read+written, one twiddle table per prime
-    achieved = alg_bytes / (fwd_ms * 1e-3) / 1e9
+    # forward: coefficients read + written, one direction's twiddle pairs per prime
+    fwd_bytes = 16 * N * limbs + 16 * N * L
+    # product: b, NTT(a), acc read and acc written; both directions' twiddle pairs per prime
+    prod_bytes = 32 * N * limbs + 32 * N * L
+    counted = (N, limbs) == (16384, 4096)
+
+    def roof(kernel, desc, alg, ms):
+        a = alg / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(a / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(COUNTERS_N16384, kernel) if counted else None,
+                "kernel": desc, "avg_ms": round(ms, 4), "alg_bytes": alg,
+                "valu_issue_frac": valu_share(COUNTERS_N16384, kernel, ms) if counted else None}
 
     out = {
         "metric": "forward NTTs/s at N=2^14 (RNS product pipeline, 8 x 50-bit limbs)",
@@ -421,11 +453,10 @@ def main():
         "config": {"workload": "rns_product_n16384_l8", "N": N, "limbs": L, "polys_per_step": B,
                    "step": "fwd(a) 1->4; then per limb on chip: fwd(b) 1->4, modmul f=4, inv 1->1, acc add",
                    "forward_ntts_per_step": fwd_per_step},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(TRAFFIC_FWD_N16384) if (N, limbs) == (16384, 4096) else None,
-                     "kernel": "ntt_onchip_kernel<fwd, N=2^14>: forward NTT of %d limbs, one launch" % limbs,
-                     "avg_ms": round(fwd_ms, 4), "alg_bytes": alg_bytes},
+        "roofline": roof("product", "ntt_onchip_product_kernel<N=2^14>: per limb forward(b), multiply, "
+                         "inverse, accumulate; %d limbs, one launch" % limbs, prod_bytes, prod_ms),
+        "roofline_fwd": roof("forward", "ntt_onchip_kernel<fwd, N=2^14>: forward NTT of %d limbs, one launch"
+                             % limbs, fwd_bytes, fwd_ms),
         "step_kernels_ms": {"fwd_lazy": round(fwd_ms, 4), "fwd_mul_inv_acc_fused": round(prod_ms, 4)},
         "fwd_ntt_rate": round(limbs / (fwd_ms * 1e-3), 1),
         "products_per_s": round(limbs / (wall / args.steps), 1),

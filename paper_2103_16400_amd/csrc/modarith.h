@@ -105,12 +105,14 @@ __device__ __forceinline__ void harvey_inv_last_c(u64& x0, u64& x1, u64 ni, u64 
 // outputs in [0, 4q):  X0 <- X0 + W X1,  X1 <- X0 - W X1  (mod q).
 // nq = 2^64 - q, nq2 = 2^64 - 2q.  Only P = v[124:125] and T = v[126:127]
 // are used: once Q has served its low-word product, its pair holds the 32-bit
-// cross products.  X1 is written last, so it may reuse an input register; X0
-// is written before the last read of 2q and is therefore early-clobber (an
+// cross products.  X1 is written last (its two halves by the final
+// subtraction), so it may reuse an input register; X0 is written before the
+// last read of 2q and is therefore early-clobber (an
 // "s" operand can end up in a VGPR where the compiler cannot keep it uniform,
 // e.g. inside a non-inlined function).
 __device__ __forceinline__ void harvey_fwd(u64& x0, u64& x1, u64 w, u64 wp, u64 q2, u64 nq, u64 nq2) {
-  u64 k, c, j, b, y0, y1;
+  u64 k, c, j, b, y0;
+  u32 y1l, y1h;
   asm volatile("v_cmp_le_u64 %[k], %[q2], %[x0]\n\t"                 // x0 >= 2q
       "v_mad_u64_u32 v[124:125], %[j], %[pl], %[x1l], 0\n\t"        // P = MulHi(W', X1) ...
       "v_lshrrev_b64 v[124:125], 32, v[124:125]\n\t"
@@ -132,34 +134,36 @@ __device__ __forceinline__ void harvey_fwd(u64& x0, u64& x1, u64 w, u64 wp, u64 
       "v_cndmask_b32 v125, %[x0h], v125, %[k]\n\t"                  // A = x0 mod 2q in [0, 2q)
       "v_lshl_add_u64 %[y0], v[124:125], 0, v[126:127]\n\t"         // X0 = A + T
       "v_lshl_add_u64 v[124:125], v[124:125], 0, %[q2]\n\t"         // A + 2q
-      "v_sub_co_u32 v124, %[b], v124, v126\n\t"
+      "v_sub_co_u32 %[y1l], %[b], v124, v126\n\t"
       "s_nop 1\n\t"
-      "v_subb_co_u32 v125, %[b], v125, v127, %[b]\n\t"
-      "v_lshl_add_u64 %[y1], v[124:125], 0, 0"                       // X1 = A + 2q - T
-      : [y0] "=&v"(y0), [y1] "=v"(y1), [k] "=&s"(k), [c] "=&s"(c), [j] "=&s"(j), [b] "=&s"(b)
+      "v_subb_co_u32 %[y1h], %[b], v125, v127, %[b]"                 // X1 = A + 2q - T
+      : [y0] "=&v"(y0), [y1l] "=v"(y1l), [y1h] "=v"(y1h), [k] "=&s"(k), [c] "=&s"(c), [j] "=&s"(j),
+        [b] "=&s"(b)
       : [x0] "v"(x0), [x0l] "v"(lo32(x0)), [x0h] "v"(hi32(x0)), [x1l] "v"(lo32(x1)), [x1h] "v"(hi32(x1)),
         [wl] "v"(lo32(w)), [wh] "v"(hi32(w)), [pl] "v"(lo32(wp)), [ph] "v"(hi32(wp)), [q2] "s"(q2), [nq2] "s"(nq2),
         [nql] "s"(lo32(nq)), [nqh] "s"(hi32(nq))
       : "v124", "v125", "v126", "v127");
   x0 = y0;
-  x1 = y1;
+  x1 = ((u64)y1h << 32) | y1l;
 }
 
 // Algorithm 5 (Harvey inverse butterfly), inputs in [0, 2q), outputs in
-// [0, 2q):  X0 <- X0 + X1,  X1 <- W (X0 - X1)  (mod q).  X0 is updated in
-// place; X1 is written last, so it may reuse the input registers.
+// [0, 2q):  X0 <- X0 + X1,  X1 <- W (X0 - X1)  (mod q).  The halves of X0
+// are selected straight into their output registers, before the last input
+// reads, so they are early-clobber; X1 is written last, so it may reuse the
+// input registers.
 __device__ __forceinline__ void harvey_inv(u64& x0, u64& x1, u64 w, u64 wp, u64 q2, u64 nq, u64 nq2) {
   u64 k, c, j, b, y1;
+  u32 y0l, y0h;
   asm volatile("v_lshl_add_u64 v[124:125], %[x0], 0, %[q2]\n\t"              // x0 + 2q
       "v_lshl_add_u64 v[126:127], %[x0], 0, %[x1]\n\t"              // S = x0 + x1 < 4q
       "v_sub_co_u32 v124, %[b], v124, %[x1l]\n\t"
       "v_cmp_le_u64 %[k], %[q2], v[126:127]\n\t"                    // S >= 2q
       "v_lshl_add_u64 v[122:123], v[126:127], 0, %[nq2]\n\t"        // S - 2q
       "v_subb_co_u32 v125, %[b], v125, %[x1h], %[b]\n\t"            // T = D = x0 + 2q - x1 < 4q
-      "v_cndmask_b32 v126, v126, v122, %[k]\n\t"
-      "v_cndmask_b32 v127, v127, v123, %[k]\n\t"                    // M = S mod 2q
+      "v_cndmask_b32 %[y0l], v126, v122, %[k]\n\t"
+      "v_cndmask_b32 %[y0h], v127, v123, %[k]\n\t"                  // X0 = S mod 2q
       "v_mad_u64_u32 v[122:123], %[j], %[pl], v124, 0\n\t"          // P = MulHi(W', D) ...
-      "v_lshl_add_u64 %[x0], v[126:127], 0, 0\n\t"                  // X0 = S mod 2q
       "v_lshrrev_b64 v[122:123], 32, v[122:123]\n\t"
       "v_mad_u64_u32 v[122:123], %[j], %[pl], v125, v[122:123]\n\t"
       "v_mad_u64_u32 v[122:123], %[c], %[ph], v124, v[122:123]\n\t"
@@ -173,13 +177,14 @@ __device__ __forceinline__ void harvey_inv(u64& x0, u64& x1, u64 w, u64 wp, u64 
       "v_mad_u64_u32 v[126:127], %[j], v122, %[nqh], v[126:127]\n\t"
       "v_mad_u64_u32 v[126:127], %[j], v123, %[nql], v[126:127]\n\t"
       "v_lshlrev_b64 v[126:127], 32, v[126:127]\n\t"
-      "v_lshl_add_u64 v[124:125], v[124:125], 0, v[126:127]\n\t"
-      "v_lshl_add_u64 %[y1], v[124:125], 0, 0"                       // X1 = W D mod q in [0, 2q)
-      : [x0] "+v"(x0), [y1] "=v"(y1), [k] "=&s"(k), [c] "=&s"(c), [j] "=&s"(j), [b] "=&s"(b)
-      : [x1] "v"(x1), [x1l] "v"(lo32(x1)), [x1h] "v"(hi32(x1)), [wl] "v"(lo32(w)), [wh] "v"(hi32(w)),
+      "v_lshl_add_u64 %[y1], v[124:125], 0, v[126:127]"              // X1 = W D mod q in [0, 2q)
+      : [y0l] "=&v"(y0l), [y0h] "=&v"(y0h), [y1] "=v"(y1), [k] "=&s"(k), [c] "=&s"(c), [j] "=&s"(j),
+        [b] "=&s"(b)
+      : [x0] "v"(x0), [x1] "v"(x1), [x1l] "v"(lo32(x1)), [x1h] "v"(hi32(x1)), [wl] "v"(lo32(w)), [wh] "v"(hi32(w)),
         [pl] "v"(lo32(wp)), [ph] "v"(hi32(wp)), [q2] "s"(q2), [nq2] "s"(nq2), [nql] "s"(lo32(nq)),
         [nqh] "s"(hi32(nq))
       : NTTAMD_CLOBBERS);
+  x0 = ((u64)y0h << 32) | y0l;
   x1 = y1;
 }
 
