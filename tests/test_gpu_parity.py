@@ -405,6 +405,55 @@ def test_poly_mul_rns(nt, logN, L, B):
     assert np.array_equal(from_dev(da), out)
 
 
+def _lazy_multiplier(tag, N, moduli):
+    """Multipliers in [0, 4q) per limb: lazy residues plus the extremes 0, q - 1, q, 2q, 4q - 1."""
+    out = _rns_inputs(tag, N, moduli, 1, 4)
+    for l, q in enumerate(moduli):
+        ext = np.array([0, q - 1, q, 2 * q, 3 * q + 1, 4 * q - 1, 4 * q - 2], dtype=np.uint64)
+        out[l * N:l * N + min(N, ext.size)] = ext[:N]
+        out[(l + 1) * N - 1] = np.uint64(4 * q - 1)
+    return out
+
+
+# Moduli from 30 to 62 bits, alone and mixed in one launch: the smallest Q-bit
+# primes, where Algorithm 8's Barrett quotient estimate is weakest, with
+# multipliers crafted up to 4q - 1 (the input factor 4 of the product step).
+MUL_EDGE_GROUPS = [[33], [58], [33, 34, 50, 57, 58], [30, 31, 32], [59], [62], [32, 33, 58, 59]]
+
+
+@pytest.mark.parametrize("logN", [10, 14])
+@pytest.mark.parametrize("bits", MUL_EDGE_GROUPS, ids=lambda b: "q" + "_".join(map(str, b)))
+def test_product_multiply_edges(nt, logN, bits):
+    """acc += InvNTT(NTT(b) (.) m) with m in [0, 4q) crafted up to 4q - 1, through the fused
+    on-chip product, against the oracle's transforms and element-wise product; and the
+    forward fused with the multiply against NTT(b) (.) (m mod q)."""
+    N = 1 << logN
+    moduli = [_edge(bt) for bt in bits]
+    L = len(moduli)
+    b = _rns_inputs(95, N, moduli, 1)
+    m = _lazy_multiplier(96, N, moduli)
+    acc0 = _rns_inputs(97, N, moduli, 1)
+    dacc = to_dev(acc0)
+    nt.poly_mul_acc_ntt_rns(dacc, to_dev(m), to_dev(b), N, moduli, 1)
+    got = from_dev(dacc)
+    dprod = empty_dev(N * L)
+    nt.ntt_forward_mul_rns(dprod, to_dev(b), to_dev(m), N, moduli, 1)
+    prod = from_dev(dprod)
+    idx = _sample_idx(N, 98, 16)
+    for l, q in enumerate(moduli):
+        s = slice(l * N, (l + 1) * N)
+        psi = oracle.min_root(N, q)
+        fb = oracle.ntt_forward(b[s], q, psi)
+        pm = oracle.eltwise_mult(fb, m[s] % np.uint64(q), q)
+        assert np.array_equal(prod[s], pm), ("fwd_mul", bits, l)
+        if N <= 1024:
+            want = oracle.eltwise_add(acc0[s], oracle.ntt_inverse(pm, q, psi), q)
+            assert np.array_equal(got[s], want), ("product", bits, l)
+        else:
+            want = oracle.eltwise_add(acc0[s][idx], oracle.ntt_inverse_at(pm, idx, q, psi), q)
+            assert np.array_equal(got[s][idx], want), ("product", bits, l)
+
+
 @pytest.mark.parametrize("logN,L,B", [(1, 1, 2), (6, 2, 2), (10, 3, 2), (12, 4, 1), (13, 2, 2), (14, 8, 2),
                                       (15, 2, 1), (17, 1, 1)])
 def test_poly_mul_acc_ntt(nt, logN, L, B):
