@@ -49,6 +49,9 @@ def lib():
             ("or_negacyclic_mul_at", None, [_U64P, _U64P, _U64P, _U64P, _U64, _U64, _U64, ctypes.c_int]),
             ("or_harvey_forward", None, [_U64P, _U64, _U64, _U64, ctypes.c_int]),
             ("or_harvey_inverse", None, [_U64P, _U64, _U64, _U64, ctypes.c_int]),
+            ("or_harvey_forward_w", None, [_U64P, _U64, _U64, _U64, ctypes.c_int, ctypes.c_int]),
+            ("or_harvey_inverse_w", None, [_U64P, _U64, _U64, _U64, ctypes.c_int, ctypes.c_int]),
+            ("or_harvey_fwd_bfly_w", None, [_U64P, _U64P, _U64, _U64, _U64, ctypes.c_int]),
         ]:
             f = getattr(L, name)
             f.restype = res
@@ -184,3 +187,32 @@ def harvey_inverse(a, q, psi, out_f=2):
     a = _arr(a).copy()
     lib().or_harvey_inverse(_p(a), a.size, q, psi, out_f)
     return a
+
+
+def _check_word(q, bits):
+    if bits not in (32, 64) or (bits == 32 and 4 * q >= (1 << 32)):
+        raise ValueError("word size 2^32 needs 4q < 2^32; bits must be 32 or 64")
+
+
+def harvey_forward_w(a, q, psi, out_f=4, bits=64):
+    """Algorithm 2 with Algorithm 4 butterflies at word size 2^bits (64, or 32 for q < 2^30)."""
+    _check_word(q, bits)
+    a = _arr(a).copy()
+    lib().or_harvey_forward_w(_p(a), a.size, q, psi, out_f, bits)
+    return a
+
+
+def harvey_inverse_w(a, q, psi, out_f=2, bits=64):
+    """Algorithm 3 with Algorithm 5 butterflies at word size 2^bits, then N^{-1}."""
+    _check_word(q, bits)
+    a = _arr(a).copy()
+    lib().or_harvey_inverse_w(_p(a), a.size, q, psi, out_f, bits)
+    return a
+
+
+def harvey_fwd_bfly_w(x0, x1, w, q, bits=64):
+    """One Algorithm 4 butterfly per element pair at word size 2^bits; returns (X0', X1')."""
+    _check_word(q, bits)
+    x0, x1 = _arr(x0).copy(), _arr(x1).copy()
+    lib().or_harvey_fwd_bfly_w(_p(x0), _p(x1), x0.size, w, q, bits)
+    return x0, x1

@@ -30,7 +30,9 @@
  *
  * The Harvey model (or_harvey_*) replays Algorithm 2 with the butterfly of
  * Algorithm 4 and Algorithm 3 with the butterfly of Algorithm 5 at word size
- * beta = 2^64, to pin the lazy output ranges the paper states.  Its N^{-1}
+ * beta = 2^64 (or_harvey_forward / _inverse) or beta = 2^32 for moduli below
+ * 2^30 (the _w variants), to pin the lazy output ranges the paper states and
+ * the representatives a word-size-beta implementation produces.  Its N^{-1}
  * step is one Shoup multiplication of each [0, 2q) value (the paper leaves
  * the representative open).
  *
@@ -318,36 +320,44 @@ void or_negacyclic_mul_at(uint64_t* c, const uint64_t* a, const uint64_t* b, con
   run_schoolbook(c, a, b, idx, count, N, q, nthreads);
 }
 
-/* ---- Harvey model: Algorithms 2-5 replayed with beta = 2^64 -------------- */
+/* ---- Harvey model: Algorithms 2-5 replayed at word size beta -------------- */
+/* Algorithms 4 and 5 are stated for a machine word of size beta (the paper's
+ * scalar path uses beta = 2^64, its IFMA path beta = 2^52).  The model takes
+ * beta = 2^bits with bits = 64 or 32; beta = 2^32 requires 4q < 2^32.  All
+ * "mod beta" arithmetic is unsigned arithmetic masked to bits. */
+
+static uint64_t word_mask(int bits) { return bits == 64 ? ~0ull : ((1ull << bits) - 1); }
 
 /* W' = floor(W * beta / q) (Algorithm 4/5 requirement). */
-static uint64_t shoup_precon(uint64_t w, uint64_t q) { return (uint64_t)(((u128)w << 64) / q); }
+static uint64_t shoup_precon_w(uint64_t w, uint64_t q, int bits) { return (uint64_t)(((u128)w << bits) / q); }
 
 /* Algorithm 4: lazy forward butterfly on [0, 4q). */
-static void harvey_fwd_bfly(uint64_t* x0, uint64_t* x1, uint64_t w, uint64_t wp, uint64_t q) {
+static void harvey_fwd_bfly(uint64_t* x0, uint64_t* x1, uint64_t w, uint64_t wp, uint64_t q, int bits) {
+  const uint64_t M = word_mask(bits);
   uint64_t X0 = *x0, X1 = *x1;
   if (X0 >= 2 * q) X0 -= 2 * q;
-  uint64_t Q = (uint64_t)(((u128)wp * X1) >> 64);
-  uint64_t T = w * X1 - Q * q;                 /* arithmetic mod 2^64 */
+  uint64_t Q = (uint64_t)(((u128)wp * X1) >> bits);
+  uint64_t T = (w * X1 - Q * q) & M;           /* arithmetic mod beta */
   *x0 = X0 + T;
   *x1 = X0 - T + 2 * q;
 }
 
 /* Algorithm 5: lazy inverse butterfly on [0, 2q). */
-static void harvey_inv_bfly(uint64_t* x0, uint64_t* x1, uint64_t w, uint64_t wp, uint64_t q) {
+static void harvey_inv_bfly(uint64_t* x0, uint64_t* x1, uint64_t w, uint64_t wp, uint64_t q, int bits) {
+  const uint64_t M = word_mask(bits);
   uint64_t X0 = *x0, X1 = *x1;
   uint64_t Y0 = X0 + X1;
   if (Y0 >= 2 * q) Y0 -= 2 * q;
   uint64_t T = X0 - X1 + 2 * q;
-  uint64_t Q = (uint64_t)(((u128)wp * T) >> 64);
+  uint64_t Q = (uint64_t)(((u128)wp * T) >> bits);
   *x0 = Y0;
-  *x1 = w * T - Q * q;                         /* arithmetic mod 2^64 */
+  *x1 = (w * T - Q * q) & M;                   /* arithmetic mod beta */
 }
 
-/* Algorithm 2 (Cooley-Tukey, merged psi) with Algorithm 4 butterflies, in
- * place.  Input values must be < 4q.  out_f = 4 leaves [0, 4q); out_f = 1
- * reduces to [0, q) by conditional subtraction of 2q then q. */
-void or_harvey_forward(uint64_t* a, uint64_t N, uint64_t q, uint64_t psi, int out_f) {
+/* Algorithm 2 (Cooley-Tukey, merged psi) with Algorithm 4 butterflies at word
+ * size 2^bits, in place.  Input values must be < 4q.  out_f = 4 leaves
+ * [0, 4q); out_f = 1 reduces to [0, q) by conditional subtraction of 2q then q. */
+void or_harvey_forward_w(uint64_t* a, uint64_t N, uint64_t q, uint64_t psi, int out_f, int bits) {
   const int logn = ilog2(N);
   uint64_t* psi_rev = (uint64_t*)malloc(sizeof(uint64_t) * N);
   for (uint64_t k = 0; k < N; ++k) psi_rev[k] = or_powmod(psi, or_brv(k, logn), q);
@@ -355,8 +365,8 @@ void or_harvey_forward(uint64_t* a, uint64_t N, uint64_t q, uint64_t psi, int ou
   for (uint64_t m = 1; m < N; m *= 2) {
     t /= 2;
     for (uint64_t i = 0; i < m; ++i) {
-      uint64_t j1 = 2 * i * t, w = psi_rev[m + i], wp = shoup_precon(w, q);
-      for (uint64_t j = j1; j < j1 + t; ++j) harvey_fwd_bfly(&a[j], &a[j + t], w, wp, q);
+      uint64_t j1 = 2 * i * t, w = psi_rev[m + i], wp = shoup_precon_w(w, q, bits);
+      for (uint64_t j = j1; j < j1 + t; ++j) harvey_fwd_bfly(&a[j], &a[j + t], w, wp, q, bits);
     }
   }
   if (out_f == 1) {
@@ -368,11 +378,12 @@ void or_harvey_forward(uint64_t* a, uint64_t N, uint64_t q, uint64_t psi, int ou
   free(psi_rev);
 }
 
-/* Algorithm 3 (Gentleman-Sande) with Algorithm 5 butterflies, then the
- * multiplication by N^{-1}, in place.  Input values must be < 2q.  out_f = 2
- * leaves [0, 2q); out_f = 1 reduces to [0, q). */
-void or_harvey_inverse(uint64_t* a, uint64_t N, uint64_t q, uint64_t psi, int out_f) {
+/* Algorithm 3 (Gentleman-Sande) with Algorithm 5 butterflies at word size
+ * 2^bits, then the multiplication by N^{-1}, in place.  Input values must be
+ * < 2q.  out_f = 2 leaves [0, 2q); out_f = 1 reduces to [0, q). */
+void or_harvey_inverse_w(uint64_t* a, uint64_t N, uint64_t q, uint64_t psi, int out_f, int bits) {
   const int logn = ilog2(N);
+  const uint64_t M = word_mask(bits);
   uint64_t psi_inv = or_invmod(psi, q);
   uint64_t* inv_rev = (uint64_t*)malloc(sizeof(uint64_t) * N);
   for (uint64_t k = 0; k < N; ++k) inv_rev[k] = or_powmod(psi_inv, or_brv(k, logn), q);
@@ -380,19 +391,34 @@ void or_harvey_inverse(uint64_t* a, uint64_t N, uint64_t q, uint64_t psi, int ou
   for (uint64_t m = N; m > 1; m /= 2) {
     uint64_t j1 = 0, h = m / 2;
     for (uint64_t i = 0; i < h; ++i) {
-      uint64_t w = inv_rev[h + i], wp = shoup_precon(w, q);
-      for (uint64_t j = j1; j < j1 + t; ++j) harvey_inv_bfly(&a[j], &a[j + t], w, wp, q);
+      uint64_t w = inv_rev[h + i], wp = shoup_precon_w(w, q, bits);
+      for (uint64_t j = j1; j < j1 + t; ++j) harvey_inv_bfly(&a[j], &a[j + t], w, wp, q, bits);
       j1 += 2 * t;
     }
     t *= 2;
   }
-  uint64_t ninv = or_invmod(N % q, q), ninvp = shoup_precon(ninv, q);
+  uint64_t ninv = or_invmod(N % q, q), ninvp = shoup_precon_w(ninv, q, bits);
   for (uint64_t j = 0; j < N; ++j) {
-    uint64_t Q = (uint64_t)(((u128)ninvp * a[j]) >> 64);
-    a[j] = ninv * a[j] - Q * q;                /* [0, 2q) */
+    uint64_t Q = (uint64_t)(((u128)ninvp * a[j]) >> bits);
+    a[j] = (ninv * a[j] - Q * q) & M;          /* [0, 2q) */
     if (out_f == 1 && a[j] >= q) a[j] -= q;
   }
   free(inv_rev);
+}
+
+/* The scalar path of the paper: beta = 2^64. */
+void or_harvey_forward(uint64_t* a, uint64_t N, uint64_t q, uint64_t psi, int out_f) {
+  or_harvey_forward_w(a, N, q, psi, out_f, 64);
+}
+void or_harvey_inverse(uint64_t* a, uint64_t N, uint64_t q, uint64_t psi, int out_f) {
+  or_harvey_inverse_w(a, N, q, psi, out_f, 64);
+}
+
+/* One Algorithm 4 butterfly at word size 2^bits on each (x0[i], x1[i]) with
+ * the same (w, w'), for brute-force checks of the butterfly alone. */
+void or_harvey_fwd_bfly_w(uint64_t* x0, uint64_t* x1, uint64_t n, uint64_t w, uint64_t q, int bits) {
+  const uint64_t wp = shoup_precon_w(w, q, bits);
+  for (uint64_t i = 0; i < n; ++i) harvey_fwd_bfly(&x0[i], &x1[i], w, wp, q, bits);
 }
 
 /* The `count` smallest primes p in [2^(bits-1), 2^bits) with p = 1 mod m,

@@ -217,3 +217,78 @@ def test_listing_product_pipeline_matches_schoolbook(golden_primes):
         fb = oracle.harvey_forward(b, q, psi, 4)
         c = oracle.harvey_inverse(oracle.eltwise_mult(fa, fb, q), q, psi, 1)
         assert np.array_equal(c, oracle.negacyclic_mul(a, b, q))
+
+
+# ---- word size beta = 2^32 (moduli below 2^30) --------------------------------
+
+def _small_moduli(golden_primes, N):
+    """Moduli below 2^30 with q = 1 mod 2N: the two smallest 30-bit primes = 1 mod 2^18,
+    and 12289 = 3 * 2^12 + 1 or 17 where N allows."""
+    qs = list(golden_primes["edge"]["by_bits"]["30"])
+    if (12289 - 1) % (2 * N) == 0:
+        qs.append(12289)
+    if (17 - 1) % (2 * N) == 0:
+        qs.append(17)
+    return qs
+
+
+@pytest.mark.parametrize("logn", [1, 2, 3, 6, 10, 12])
+def test_harvey_word32_model_agrees_with_direct_and_keeps_lazy_ranges(logn, golden_primes):
+    """Algorithms 2-5 at beta = 2^32 give the direct definition mod q, within the
+    lazy ranges of Algorithms 4 and 5, for inputs up to the largest input factor."""
+    N = 1 << logn
+    for q in _small_moduli(golden_primes, N):
+        psi = oracle.min_root(N, q)
+        for in_f in (1, 2, 4):
+            a = lazy_mod(unit_seed(40, logn, q, in_f), N, q, in_f)
+            if in_f == 4:
+                a[-1] = np.uint64(4 * q - 1)
+            ref = oracle.ntt_forward(a, q, psi)
+            lazy = oracle.harvey_forward_w(a, q, psi, out_f=4, bits=32)
+            assert np.all(lazy < np.uint64(4 * q))
+            assert np.array_equal(lazy % np.uint64(q), ref)
+            assert np.array_equal(oracle.harvey_forward_w(a, q, psi, out_f=1, bits=32), ref)
+        for in_f in (1, 2):
+            A = lazy_mod(unit_seed(41, logn, q, in_f), N, q, in_f)
+            ref = oracle.ntt_inverse(A, q, psi)
+            lazy = oracle.harvey_inverse_w(A, q, psi, out_f=2, bits=32)
+            assert np.all(lazy < np.uint64(2 * q))
+            assert np.array_equal(lazy % np.uint64(q), ref)
+            assert np.array_equal(oracle.harvey_inverse_w(A, q, psi, out_f=1, bits=32), ref)
+
+
+def test_harvey_word_size_parameter(golden_primes):
+    """At beta = 2^64 the parameterised model is the scalar model; at beta = 2^32
+    the representatives are the ones a 32-bit word produces, not the 64-bit ones."""
+    N = 1024
+    q = golden_primes["edge"]["by_bits"]["30"][0]
+    psi = oracle.min_root(N, q)
+    a = lazy_mod(unit_seed(42), N, q, 4)
+    f64 = oracle.harvey_forward(a, q, psi, 4)
+    assert np.array_equal(oracle.harvey_forward_w(a, q, psi, 4, bits=64), f64)
+    f32 = oracle.harvey_forward_w(a, q, psi, 4, bits=32)
+    assert np.array_equal(f32 % np.uint64(q), f64 % np.uint64(q))
+    assert not np.array_equal(f32, f64)
+    with pytest.raises(ValueError):
+        oracle.harvey_forward_w(a, golden_primes["edge"]["by_bits"]["31"][0], psi, 4, bits=32)
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+def test_harvey_butterfly_brute_force(bits, golden_primes):
+    """One Algorithm 4 butterfly on many (X0, X1) pairs, against exact integer
+    arithmetic: X0' = A + T and X1' = A + 2q - T with A = X0 mod 2q (X0 < 4q),
+    T = W X1 mod q taken in [0, 2q); both outputs below 4q."""
+    for q in list(golden_primes["edge"]["by_bits"]["30"]) + [12289, 17]:
+        n = 4000
+        x0 = lazy_mod(unit_seed(43, q, bits), n, q, 4)
+        x1 = lazy_mod(unit_seed(44, q, bits), n, q, 4)
+        x0[:3] = np.array([0, 2 * q, 4 * q - 1], dtype=np.uint64)
+        x1[:3] = np.array([4 * q - 1, 0, 4 * q - 1], dtype=np.uint64)
+        for w in [1, q - 1, int(uniform_mod(unit_seed(45, q), 1, q)[0])]:
+            y0, y1 = oracle.harvey_fwd_bfly_w(x0, x1, w, q, bits)
+            for i in range(0, n, 7):
+                X0, X1 = int(x0[i]), int(x1[i])
+                A = X0 - 2 * q if X0 >= 2 * q else X0
+                T = int(y0[i]) - A
+                assert 0 <= T < 2 * q and T % q == (w * X1) % q, (q, w, X0, X1)
+                assert int(y1[i]) == A + 2 * q - T and int(y0[i]) < 4 * q and int(y1[i]) < 4 * q
