@@ -311,6 +311,53 @@ def time_serving(nt, torch, primes, rates=SERVE_RATES, max_requests=4000, second
     return res
 
 
+def time_small_primes(nt, torch, primes, B=512, steps=20, warmup=5):
+    """The step of the headline (forward of a, then the fused on-chip product into acc) at
+    word size 2^32: N = 2^14, 8 limbs of primes below 2^30, 4-byte coefficients."""
+    p = primes["small_16384"]
+    N, moduli = p["N"], p["moduli"]
+    L = len(moduli)
+    dev = torch.device("cuda:0")
+    a = torch.from_numpy(gen_operand(11, N, moduli, B).astype(np.uint32).view(np.int32)).to(dev)
+    b = torch.from_numpy(gen_operand(12, N, moduli, B).astype(np.uint32).view(np.int32)).to(dev)
+    c = torch.empty_like(a)
+    acc = torch.zeros_like(a)
+    stream = torch.cuda.current_stream()
+    ev = []
+
+    def step(record):
+        es = [torch.cuda.Event(enable_timing=True) for _ in range(3)] if record else None
+        if record:
+            es[0].record(stream)
+        nt.ntt_forward_rns32(c, a, N, moduli, B, 1, 4, stream=stream)
+        if record:
+            es[1].record(stream)
+        nt.poly_mul_acc_ntt_rns32(acc, c, b, N, moduli, B, stream=stream)
+        if record:
+            es[2].record(stream)
+            ev.append(es)
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    prod_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    limbs = B * L
+    fwd_bytes = 8 * N * limbs + 16 * N * L         # 4-byte coefficients read + written; 16-byte twiddle pairs
+    prod_bytes = 16 * N * limbs + 32 * N * L       # b, NTT(a), acc read, acc written; both directions' pairs
+    return {"N": N, "limbs": L, "polys": B, "moduli_bits": 30, "word_bits": 32,
+            "forward_ntts_per_s": round(2 * limbs / wall, 1), "ms_per_step": round(wall * 1e3, 4),
+            "fwd_lazy_ms": round(fwd_ms, 4), "fwd_hbm_frac": round(fwd_bytes / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "product_ms": round(prod_ms, 4),
+            "product_hbm_frac": round(prod_bytes / (prod_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "fwd_limb_ntts_per_s": round(limbs / (fwd_ms * 1e-3), 1)}
+
+
 def time_single_1024(nt, torch, primes, reps=200):
     """Per-call latency of one forward and one inverse NTT at N = 1024 (single limb)."""
     p1 = primes["single_1024"]
@@ -466,6 +513,7 @@ def main():
         torch.cuda.empty_cache()
         out["large_ring_n65536_l32"] = time_large_ring(nt, torch, load_primes())
         out["single_n1024"] = time_single_1024(nt, torch, load_primes())
+        out["small_primes_n16384_l8"] = time_small_primes(nt, torch, load_primes())
         out["uneven_batch_256polys"] = time_uneven_batch(nt, torch, load_primes())
         if not args.no_serve:
             out["serving"] = time_serving(nt, torch, load_primes(), max_requests=args.serve_requests,

@@ -249,6 +249,45 @@ ntt_status poly_mul_acc_ntt_rns(uint64_t* acc, const uint64_t* a_ntt, const uint
                                 const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys, uint64_t* workspace,
                                 ntt_stream_t stream);
 
+/* ---- Small moduli: word size 2^32 ---------------------------------------
+ * Algorithms 2-5 (Section 3) at machine word beta = 2^32 instead of 2^64, for
+ * moduli q < 2^30 (so that the lazy range 4q fits a 32-bit word), prime,
+ * q = 1 mod 2N, and N a power of two in [2, 2^14]: the analogue of the
+ * paper's size-specialised IFMA52 path (Algorithms 6 and 7, beta = 2^52 for
+ * q < 2^50).  Coefficients are uint32_t, laid out like the 64-bit calls
+ * ([num_polys][num_limbs][N], limb l under moduli[l]); every product is a
+ * native 32 x 32-bit multiply and every coefficient moves 4 bytes.
+ *
+ * Ranges and factors are those of the 64-bit calls: the forward takes inputs
+ * in [0, f q), f in {1, 2, 4}, and returns [0, 4q) (output factor 4, the words
+ * Algorithm 4 produces at beta = 2^32) or [0, q) (factor 1); the inverse takes
+ * [0, f q), f in {1, 2}, and returns [0, 2q) or [0, q), with N^{-1} fused into
+ * its last stage.  Each call is one launch of one workgroup per limb.
+ *
+ * Errors: NTT_EINVAL_MODULUS for a modulus of 2^30 or more (or one that is
+ * not a valid NTT prime for N), NTT_EINVAL_DEGREE for N above 2^14,
+ * NTT_EINVAL_FACTOR, NTT_EINVAL_COUNT, NTT_EINVAL_POINTER, and NTT_EALIAS when
+ * an output partially overlaps an input (exact in-place is allowed where the
+ * 64-bit call allows it). */
+ntt_status ntt_forward_rns32(uint32_t* result, const uint32_t* operand, uint64_t N, const uint64_t* moduli,
+                             uint64_t num_limbs, uint64_t num_polys, uint64_t input_mod_factor,
+                             uint64_t output_mod_factor, ntt_stream_t stream);
+ntt_status ntt_inverse_rns32(uint32_t* result, const uint32_t* operand, uint64_t N, const uint64_t* moduli,
+                             uint64_t num_limbs, uint64_t num_polys, uint64_t input_mod_factor,
+                             uint64_t output_mod_factor, ntt_stream_t stream);
+/* result = a * b mod (X^N + 1, q_l) per limb, canonical (the product listing of
+ * Section 4): forward(a) in one launch, then one launch that keeps each limb
+ * on chip for forward(b), the Algorithm 8 multiply and the inverse.  a and b
+ * in [0, q); result may equal a, not b. */
+ntt_status poly_mul_rns32(uint32_t* result, const uint32_t* a, const uint32_t* b, uint64_t N, const uint64_t* moduli,
+                          uint64_t num_limbs, uint64_t num_polys, ntt_stream_t stream);
+/* acc += a * b with a given as its forward transform (a_ntt in [0, 4q), e.g.
+ * ntt_forward_rns32 with output factor 4), b in [0, q), acc canonical: one
+ * launch.  acc must not overlap a_ntt or b. */
+ntt_status poly_mul_acc_ntt_rns32(uint32_t* acc, const uint32_t* a_ntt, const uint32_t* b, uint64_t N,
+                                  const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
+                                  ntt_stream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Batches of limb tasks with uneven ring degrees in one persistent launch.
  * RNS polynomials of different sizes and limb counts (Section 5) are lists of

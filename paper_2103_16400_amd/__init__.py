@@ -57,6 +57,10 @@ _SIGS = {
     "ntt_batch_autotune": (_ST, [_P, _P, ctypes.c_size_t, _P, ctypes.POINTER(ctypes.c_int)]),
     "eltwise_fma_mod": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _P]),
     "poly_mul_acc_ntt_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P, _P]),
+    "ntt_forward_rns32": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _U64, _P]),
+    "ntt_inverse_rns32": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _U64, _P]),
+    "poly_mul_rns32": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P]),
+    "poly_mul_acc_ntt_rns32": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P]),
     "eltwise_fma_mod_rns": (_ST, [_P, _P, _P, _P, _U64, _P, _U64, _U64, _U64, _P]),
     "eltwise_sub_mod": (_ST, [_P, _P, _P, _U64, _U64, _P]),
     "eltwise_negate_mod": (_ST, [_P, _P, _U64, _U64, _P]),
@@ -114,19 +118,24 @@ def _check(status: int, what: str):
         raise NttError(status, what)
 
 
-def _ptr(t):
+def _ptr(t, bits=64):
     if t is None:
         return None
     import torch
     if not isinstance(t, torch.Tensor):
         raise TypeError("expected a torch tensor")
-    if t.dtype not in (torch.uint64, torch.int64):
-        raise TypeError("expected a uint64 (or int64) tensor, got %s" % t.dtype)
+    ok = (torch.uint64, torch.int64) if bits == 64 else (torch.uint32, torch.int32)
+    if t.dtype not in ok:
+        raise TypeError("expected a uint%d (or int%d) tensor, got %s" % (bits, bits, t.dtype))
     if not t.is_cuda:
         raise ValueError("tensor must be on a ROCm device")
     if not t.is_contiguous():
         raise ValueError("tensor must be contiguous")
     return t.data_ptr()
+
+
+def _ptr32(t):
+    return _ptr(t, 32)
 
 
 def _stream(stream):
@@ -318,6 +327,34 @@ def poly_mul_acc_ntt_rns(acc, a_ntt, b, N, moduli, num_polys, workspace=None, st
     m, L = _moduli(moduli)
     _check(_lib.poly_mul_acc_ntt_rns(_ptr(acc), _ptr(a_ntt), _ptr(b), N, m, L, num_polys, _ptr(workspace),
                                      _stream(stream)), "poly_mul_acc_ntt_rns")
+
+
+def ntt_forward_rns32(result, operand, N, moduli, num_polys, input_mod_factor=1, output_mod_factor=1, stream=None):
+    """Forward NTT at word size 2^32 (moduli below 2^30, N <= 2^14); uint32 coefficients."""
+    m, L = _moduli(moduli)
+    _check(_lib.ntt_forward_rns32(_ptr32(result), _ptr32(operand), N, m, L, num_polys, input_mod_factor,
+                                  output_mod_factor, _stream(stream)), "ntt_forward_rns32")
+
+
+def ntt_inverse_rns32(result, operand, N, moduli, num_polys, input_mod_factor=1, output_mod_factor=1, stream=None):
+    """Inverse NTT at word size 2^32 (moduli below 2^30, N <= 2^14); uint32 coefficients."""
+    m, L = _moduli(moduli)
+    _check(_lib.ntt_inverse_rns32(_ptr32(result), _ptr32(operand), N, m, L, num_polys, input_mod_factor,
+                                  output_mod_factor, _stream(stream)), "ntt_inverse_rns32")
+
+
+def poly_mul_rns32(result, a, b, N, moduli, num_polys, stream=None):
+    """result = a * b mod (X^N + 1, q_l) per limb at word size 2^32."""
+    m, L = _moduli(moduli)
+    _check(_lib.poly_mul_rns32(_ptr32(result), _ptr32(a), _ptr32(b), N, m, L, num_polys, _stream(stream)),
+           "poly_mul_rns32")
+
+
+def poly_mul_acc_ntt_rns32(acc, a_ntt, b, N, moduli, num_polys, stream=None):
+    """acc += a * b at word size 2^32, with a given as its forward NTT (lazy outputs allowed)."""
+    m, L = _moduli(moduli)
+    _check(_lib.poly_mul_acc_ntt_rns32(_ptr32(acc), _ptr32(a_ntt), _ptr32(b), N, m, L, num_polys, _stream(stream)),
+           "poly_mul_acc_ntt_rns32")
 
 
 def eltwise_fma_mod(result, arg1, arg2, arg3, n, modulus, input_mod_factor=1, stream=None):

@@ -77,6 +77,26 @@ ntt_status ntt_rns(bool fwd, uint64_t* result, const uint64_t* operand, const ui
   return fwd ? launch_forward(l) : launch_inverse(l);
 }
 
+// Word-size-2^32 path: moduli below 2^30 (4q < 2^32), N in [2, 2^14].
+ntt_status small_call(uint32_t op, uint32_t* out, const uint32_t* in, const uint32_t* mul, uint64_t N,
+                      const uint64_t* moduli, uint64_t L, uint64_t B, ntt_stream_t stream) {
+  if (!out || !in || !moduli) return NTT_EINVAL_POINTER;
+  if (B == 0 || L == 0 || L > NTT_MAX_LIMBS) return NTT_EINVAL_COUNT;
+  ntt_status st = validate_degree(N);
+  if (st) return st;
+  int logN = 0;
+  while ((1ull << logN) < N) ++logN;
+  if (logN > kMaxOnchipLog) return NTT_EINVAL_DEGREE;
+  for (uint64_t i = 0; i < L; ++i)
+    if (moduli[i] >= (1ull << 30)) return NTT_EINVAL_MODULUS;
+  if (B > (1ull << 40) / (L * N)) return NTT_EINVAL_COUNT;
+  std::vector<const ntt_plan*> plans;
+  st = rns_plans(N, moduli, L, plans);
+  if (st) return st;
+  Small32Launch l{out, in, mul, plans.data(), (uint32_t)L, B, logN, op, (hipStream_t)stream};
+  return launch_small(l);
+}
+
 // Second half of a fused product for N <= 2^14 (one launch): out = InvNTT(NTT(b) (.) m),
 // or out += it; m = NTT(a), lazy.
 ntt_status product_rns(bool acc, uint64_t* out, const uint64_t* b, const uint64_t* m, uint64_t N,
@@ -406,6 +426,58 @@ ntt_status poly_mul_acc_ntt_rns(uint64_t* acc, const uint64_t* a_ntt, const uint
   st = ntt_rns(true, prod, b, a_ntt, mid, N, moduli, num_limbs, num_polys, 1, 4, stream);
   if (st) return st;
   return ntt_rns(false, acc, prod, acc, prod, N, moduli, num_limbs, num_polys, 1, 1, stream);
+}
+
+ntt_status ntt_forward_rns32(uint32_t* result, const uint32_t* operand, uint64_t N, const uint64_t* moduli,
+                             uint64_t num_limbs, uint64_t num_polys, uint64_t input_mod_factor,
+                             uint64_t output_mod_factor, ntt_stream_t stream) {
+  ntt_status st = check_fwd_factors(input_mod_factor, output_mod_factor);
+  if (st) return st;
+  if (num_limbs && num_polys && N && num_polys <= (1ull << 40) / (num_limbs * N)) {
+    st = check_alias(result, operand, (size_t)(num_polys * num_limbs * N * sizeof(uint32_t)));
+    if (st) return st;
+  }
+  return small_call(output_mod_factor == 1 ? kSmallForwardCanon : kSmallForwardLazy, result, operand, nullptr, N,
+                    moduli, num_limbs, num_polys, stream);
+}
+
+ntt_status ntt_inverse_rns32(uint32_t* result, const uint32_t* operand, uint64_t N, const uint64_t* moduli,
+                             uint64_t num_limbs, uint64_t num_polys, uint64_t input_mod_factor,
+                             uint64_t output_mod_factor, ntt_stream_t stream) {
+  ntt_status st = check_inv_factors(input_mod_factor, output_mod_factor);
+  if (st) return st;
+  if (num_limbs && num_polys && N && num_polys <= (1ull << 40) / (num_limbs * N)) {
+    st = check_alias(result, operand, (size_t)(num_polys * num_limbs * N * sizeof(uint32_t)));
+    if (st) return st;
+  }
+  return small_call(output_mod_factor == 1 ? kSmallInverseCanon : kSmallInverseLazy, result, operand, nullptr, N,
+                    moduli, num_limbs, num_polys, stream);
+}
+
+ntt_status poly_mul_acc_ntt_rns32(uint32_t* acc, const uint32_t* a_ntt, const uint32_t* b, uint64_t N,
+                                  const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
+                                  ntt_stream_t stream) {
+  if (!acc || !a_ntt || !b) return NTT_EINVAL_POINTER;
+  if (num_limbs && num_polys && N && num_polys <= (1ull << 40) / (num_limbs * N)) {
+    const size_t bytes = (size_t)(num_polys * num_limbs * N * sizeof(uint32_t));
+    if (overlaps(acc, bytes, a_ntt, bytes) || overlaps(acc, bytes, b, bytes)) return NTT_EALIAS;
+  }
+  return small_call(kSmallProductAcc, acc, b, a_ntt, N, moduli, num_limbs, num_polys, stream);
+}
+
+ntt_status poly_mul_rns32(uint32_t* result, const uint32_t* a, const uint32_t* b, uint64_t N, const uint64_t* moduli,
+                          uint64_t num_limbs, uint64_t num_polys, ntt_stream_t stream) {
+  if (!result || !a || !b) return NTT_EINVAL_POINTER;
+  if (num_limbs && num_polys && N && num_polys <= (1ull << 40) / (num_limbs * N)) {
+    const size_t bytes = (size_t)(num_polys * num_limbs * N * sizeof(uint32_t));
+    if (overlaps(result, bytes, b, bytes)) return NTT_EALIAS;
+    ntt_status st = check_alias(result, a, bytes);
+    if (st) return st;
+  }
+  // result <- NTT(a) in [0, 4q); then on chip: result <- InvNTT(NTT(b) (.) result), canonical
+  ntt_status st = small_call(kSmallForwardLazy, result, a, nullptr, N, moduli, num_limbs, num_polys, stream);
+  if (st) return st;
+  return small_call(kSmallProduct, result, b, result, N, moduli, num_limbs, num_polys, stream);
 }
 
 ntt_status ntt_autotune(uint64_t N, const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,

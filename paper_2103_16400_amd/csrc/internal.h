@@ -148,4 +148,21 @@ ntt_status launch_eltwise_fma(const EltLaunch& l);                // b = addend 
 ntt_status batch_launch_tasks(ntt_batch* b, const BatchTask* tasks, size_t count, hipStream_t stream, bool graph);
 ntt_status launch_eltwise_add(const EltLaunch& l);
 
+// Word-size-2^32 transforms for moduli below 2^30 and N <= 2^14 (ntt_small.hip).
+enum SmallOp : uint32_t {
+  kSmallForwardLazy, kSmallForwardCanon, kSmallInverseLazy, kSmallInverseCanon, kSmallProduct, kSmallProductAcc
+};
+struct Small32Launch {
+  uint32_t* out;
+  const uint32_t* in;
+  const uint32_t* mul;          // products: the transformed multiplier (lazy, [0, 4q))
+  const ntt_plan* const* plans; // num_limbs plans
+  uint32_t num_limbs;
+  uint64_t num_polys;
+  int logN;
+  uint32_t op;                  // SmallOp
+  hipStream_t stream;
+};
+ntt_status launch_small(const Small32Launch& l);
+
 }  // namespace nttamd

@@ -13,6 +13,8 @@ q prime, q < 2^62 and quotes timings on an unspecified 50-bit modulus):
                 so bit lengths run over 50..60
   edge          smallest primes just above 2^(Q-1), Q = 30..62, that are 1 mod
                 2^18 (Barrett's quotient estimate is weakest there)
+  small_16384   8 largest primes < 2^30 that are 1 mod 2^15 (N = 2^14, 8 limbs,
+                for the word-size-2^32 path, which needs 4q < 2^32)
 Run:  python tests/golden/make_golden.py
 """
 import json
@@ -42,6 +44,8 @@ def main():
     for Q in range(30, 63):
         edge[str(Q)] = oracle.find_primes_up(Q, 1 << 18, 2)
     out["edge"] = {"N_max": 131072, "by_bits": edge}
+    q6 = oracle.find_primes(30, 1 << 15, 8)
+    out["small_16384"] = {"N": 16384, "moduli": q6, "psi": [oracle.min_root(16384, q) for q in q6]}
     path = os.path.join(HERE, "primes.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)

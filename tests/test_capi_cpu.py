@@ -114,3 +114,35 @@ def test_server_config_validation_without_device(nt):
     assert lib.ntt_server_release(None, 1) == -5
     assert lib.ntt_server_destroy(None) == -5
     assert lib.ntt_server_now_ns() > 0
+
+
+def test_small_modulus_validation_without_device(nt):
+    """The word-size-2^32 calls reject moduli of 2^30 or more, N above 2^14, bad
+    factors, null pointers, empty batches and partial overlaps before any device work."""
+    L = _raw(nt)
+    fake = ctypes.c_void_p(0x1000000)
+    other = ctypes.c_void_p(0x40000000)
+    shifted = ctypes.c_void_p(0x1000000 + 4)
+    small = (ctypes.c_uint64 * 1)(1073643521)      # < 2^30, 1 mod 2^15
+    big = (ctypes.c_uint64 * 1)(1 << 30)
+    q31 = (ctypes.c_uint64 * 1)(1074266113)        # 31-bit NTT prime: 4q does not fit 32 bits
+    assert L.ntt_forward_rns32(fake, other, 1024, big, 1, 1, 1, 1, None) == nt.NTT_EINVAL_MODULUS
+    assert L.ntt_forward_rns32(fake, other, 1024, q31, 1, 1, 1, 1, None) == nt.NTT_EINVAL_MODULUS
+    assert L.ntt_inverse_rns32(fake, other, 1024, q31, 1, 1, 1, 1, None) == nt.NTT_EINVAL_MODULUS
+    assert L.ntt_forward_rns32(fake, other, 1 << 15, small, 1, 1, 1, 1, None) == nt.NTT_EINVAL_DEGREE
+    assert L.ntt_forward_rns32(fake, other, 1000, small, 1, 1, 1, 1, None) == nt.NTT_EINVAL_DEGREE
+    assert L.ntt_forward_rns32(fake, other, 1024, small, 1, 1, 3, 1, None) == nt.NTT_EINVAL_FACTOR
+    assert L.ntt_forward_rns32(fake, other, 1024, small, 1, 1, 1, 2, None) == nt.NTT_EINVAL_FACTOR
+    assert L.ntt_inverse_rns32(fake, other, 1024, small, 1, 1, 4, 1, None) == nt.NTT_EINVAL_FACTOR
+    assert L.ntt_inverse_rns32(fake, other, 1024, small, 1, 1, 1, 4, None) == nt.NTT_EINVAL_FACTOR
+    assert L.ntt_forward_rns32(None, other, 1024, small, 1, 1, 1, 1, None) == nt.NTT_EINVAL_POINTER
+    assert L.ntt_forward_rns32(fake, other, 1024, None, 1, 1, 1, 1, None) == nt.NTT_EINVAL_POINTER
+    assert L.ntt_forward_rns32(fake, other, 1024, small, 0, 1, 1, 1, None) == nt.NTT_EINVAL_COUNT
+    assert L.ntt_forward_rns32(fake, other, 1024, small, 1, 0, 1, 1, None) == nt.NTT_EINVAL_COUNT
+    assert L.ntt_forward_rns32(shifted, fake, 1024, small, 1, 1, 1, 1, None) == nt.NTT_EALIAS
+    assert L.poly_mul_rns32(fake, other, fake, 1024, small, 1, 1, None) == nt.NTT_EALIAS
+    assert L.poly_mul_rns32(fake, None, other, 1024, small, 1, 1, None) == nt.NTT_EINVAL_POINTER
+    assert L.poly_mul_acc_ntt_rns32(fake, fake, other, 1024, small, 1, 1, None) == nt.NTT_EALIAS
+    assert L.poly_mul_acc_ntt_rns32(fake, other, shifted, 1024, small, 1, 1, None) == nt.NTT_EALIAS
+    assert L.poly_mul_acc_ntt_rns32(fake, other, other, 1 << 15, small, 1, 1, None) == nt.NTT_EINVAL_DEGREE
+    assert L.poly_mul_acc_ntt_rns32(fake, other, other, 1024, big, 1, 1, None) == nt.NTT_EINVAL_MODULUS
