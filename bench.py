@@ -311,10 +311,10 @@ def time_serving(nt, torch, primes, rates=SERVE_RATES, max_requests=4000, second
     return res
 
 
-def time_small_primes(nt, torch, primes, B=512, steps=20, warmup=5):
+def time_small_primes(nt, torch, primes, key="small_16384", B=512, steps=20, warmup=5):
     """The step of the headline (forward of a, then the fused on-chip product into acc) at
-    word size 2^32: N = 2^14, 8 limbs of primes below 2^30, 4-byte coefficients."""
-    p = primes["small_16384"]
+    word size 2^32: N = 2^14 (or 2^15), 8 limbs of primes below 2^30, 4-byte coefficients."""
+    p = primes[key]
     N, moduli = p["N"], p["moduli"]
     L = len(moduli)
     dev = torch.device("cuda:0")
@@ -514,6 +514,7 @@ def main():
         out["large_ring_n65536_l32"] = time_large_ring(nt, torch, load_primes())
         out["single_n1024"] = time_single_1024(nt, torch, load_primes())
         out["small_primes_n16384_l8"] = time_small_primes(nt, torch, load_primes())
+        out["small_primes_n32768_l8"] = time_small_primes(nt, torch, load_primes(), "small_32768", B=256)
         out["uneven_batch_256polys"] = time_uneven_batch(nt, torch, load_primes())
         if not args.no_serve:
             out["serving"] = time_serving(nt, torch, load_primes(), max_requests=args.serve_requests,

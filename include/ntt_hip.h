@@ -252,7 +252,7 @@ ntt_status poly_mul_acc_ntt_rns(uint64_t* acc, const uint64_t* a_ntt, const uint
 /* ---- Small moduli: word size 2^32 ---------------------------------------
  * Algorithms 2-5 (Section 3) at machine word beta = 2^32 instead of 2^64, for
  * moduli q < 2^30 (so that the lazy range 4q fits a 32-bit word), prime,
- * q = 1 mod 2N, and N a power of two in [2, 2^14]: the analogue of the
+ * q = 1 mod 2N, and N a power of two in [2, 2^15]: the analogue of the
  * paper's size-specialised IFMA52 path (Algorithms 6 and 7, beta = 2^52 for
  * q < 2^50).  Coefficients are uint32_t, laid out like the 64-bit calls
  * ([num_polys][num_limbs][N], limb l under moduli[l]); every product is a
@@ -262,10 +262,11 @@ ntt_status poly_mul_acc_ntt_rns(uint64_t* acc, const uint64_t* a_ntt, const uint
  * in [0, f q), f in {1, 2, 4}, and returns [0, 4q) (output factor 4, the words
  * Algorithm 4 produces at beta = 2^32) or [0, q) (factor 1); the inverse takes
  * [0, f q), f in {1, 2}, and returns [0, 2q) or [0, q), with N^{-1} fused into
- * its last stage.  Each call is one launch of one workgroup per limb.
+ * its last stage.  Each call is one launch of one workgroup per limb (N = 2^15
+ * takes 132 KiB of LDS: one workgroup per CU).
  *
  * Errors: NTT_EINVAL_MODULUS for a modulus of 2^30 or more (or one that is
- * not a valid NTT prime for N), NTT_EINVAL_DEGREE for N above 2^14,
+ * not a valid NTT prime for N), NTT_EINVAL_DEGREE for N above 2^15,
  * NTT_EINVAL_FACTOR, NTT_EINVAL_COUNT, NTT_EINVAL_POINTER, and NTT_EALIAS when
  * an output partially overlaps an input (exact in-place is allowed where the
  * 64-bit call allows it). */

@@ -330,14 +330,14 @@ def poly_mul_acc_ntt_rns(acc, a_ntt, b, N, moduli, num_polys, workspace=None, st
 
 
 def ntt_forward_rns32(result, operand, N, moduli, num_polys, input_mod_factor=1, output_mod_factor=1, stream=None):
-    """Forward NTT at word size 2^32 (moduli below 2^30, N <= 2^14); uint32 coefficients."""
+    """Forward NTT at word size 2^32 (moduli below 2^30, N <= 2^15); uint32 coefficients."""
     m, L = _moduli(moduli)
     _check(_lib.ntt_forward_rns32(_ptr32(result), _ptr32(operand), N, m, L, num_polys, input_mod_factor,
                                   output_mod_factor, _stream(stream)), "ntt_forward_rns32")
 
 
 def ntt_inverse_rns32(result, operand, N, moduli, num_polys, input_mod_factor=1, output_mod_factor=1, stream=None):
-    """Inverse NTT at word size 2^32 (moduli below 2^30, N <= 2^14); uint32 coefficients."""
+    """Inverse NTT at word size 2^32 (moduli below 2^30, N <= 2^15); uint32 coefficients."""
     m, L = _moduli(moduli)
     _check(_lib.ntt_inverse_rns32(_ptr32(result), _ptr32(operand), N, m, L, num_polys, input_mod_factor,
                                   output_mod_factor, _stream(stream)), "ntt_inverse_rns32")

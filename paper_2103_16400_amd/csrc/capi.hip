@@ -77,7 +77,7 @@ ntt_status ntt_rns(bool fwd, uint64_t* result, const uint64_t* operand, const ui
   return fwd ? launch_forward(l) : launch_inverse(l);
 }
 
-// Word-size-2^32 path: moduli below 2^30 (4q < 2^32), N in [2, 2^14].
+// Word-size-2^32 path: moduli below 2^30 (4q < 2^32), N in [2, 2^15].
 ntt_status small_call(uint32_t op, uint32_t* out, const uint32_t* in, const uint32_t* mul, uint64_t N,
                       const uint64_t* moduli, uint64_t L, uint64_t B, ntt_stream_t stream) {
   if (!out || !in || !moduli) return NTT_EINVAL_POINTER;
@@ -86,7 +86,7 @@ ntt_status small_call(uint32_t op, uint32_t* out, const uint32_t* in, const uint
   if (st) return st;
   int logN = 0;
   while ((1ull << logN) < N) ++logN;
-  if (logN > kMaxOnchipLog) return NTT_EINVAL_DEGREE;
+  if (logN > kMaxSmallLog) return NTT_EINVAL_DEGREE;
   for (uint64_t i = 0; i < L; ++i)
     if (moduli[i] >= (1ull << 30)) return NTT_EINVAL_MODULUS;
   if (B > (1ull << 40) / (L * N)) return NTT_EINVAL_COUNT;

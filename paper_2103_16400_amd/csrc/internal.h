@@ -148,7 +148,8 @@ ntt_status launch_eltwise_fma(const EltLaunch& l);                // b = addend 
 ntt_status batch_launch_tasks(ntt_batch* b, const BatchTask* tasks, size_t count, hipStream_t stream, bool graph);
 ntt_status launch_eltwise_add(const EltLaunch& l);
 
-// Word-size-2^32 transforms for moduli below 2^30 and N <= 2^14 (ntt_small.hip).
+// Word-size-2^32 transforms for moduli below 2^30 and N <= 2^15 (ntt_small.hip).
+constexpr int kMaxSmallLog = 15;
 enum SmallOp : uint32_t {
   kSmallForwardLazy, kSmallForwardCanon, kSmallInverseLazy, kSmallInverseCanon, kSmallProduct, kSmallProductAcc
 };

@@ -1,5 +1,5 @@
 // Single-pass negacyclic NTT at word size beta = 2^32, for moduli below 2^30
-// and N <= 2^14: the small-prime specialisation of the transforms, the
+// and N <= 2^15: the small-prime specialisation of the transforms, the
 // counterpart of the paper's size-specialised IFMA52 path (Algorithms 6 and 7
 // run Algorithms 4 and 5 at beta = 2^52 for moduli below 2^50).
 //
@@ -20,7 +20,11 @@
 // and runs up to LOGR stages per round, rounds exchange through LDS (one
 // 32-bit word per coefficient, rows padded every 2^LOGR words), the round in
 // which a thread owns consecutive coefficients reads the plan's transposed
-// sub-tables, and HBM is read and written once per coefficient.
+// sub-tables, and HBM is read and written once per coefficient.  At 4 bytes
+// per coefficient a limb of N = 2^15 (128 KiB) still fits the LDS of one
+// workgroup (1024 threads, one workgroup per CU); the plan's transposed copy
+// at that size is laid out for the two-pass kernels, so that size reads the
+// natural tables throughout.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -115,8 +119,9 @@ struct OnChip32 {
   static constexpr int R = 1 << LOGR;
   static constexpr int NT = N >> LOGR;
   static constexpr int LDSW = N + (N >> LOGR);
-  // the transposed sub-tables are laid out for onchip_logr(LOGN) coefficients per thread
-  static constexpr int PERM_TOP = LOGR == onchip_logr(LOGN) ? onchip_perm_top(FWD, LOGN) : -1;
+  // the transposed sub-tables are laid out for onchip_logr(LOGN) coefficients per thread, for N <= 2^14
+  static constexpr int PERM_TOP =
+      LOGN <= kMaxOnchipLog && LOGR == onchip_logr(LOGN) ? onchip_perm_top(FWD, LOGN) : -1;
   static constexpr int TB = 2;                    // twiddle pairs per prefetch block
   using G = Geo<FWD, LOGN, LOGR>;
 
@@ -335,6 +340,7 @@ static Kernel32 pick32(int logN) {
     case 12: return ntt32_kernel<FWD, 12, MODE>;
     case 13: return ntt32_kernel<FWD, 13, MODE>;
     case 14: return ntt32_kernel<FWD, 14, MODE>;
+    case 15: return ntt32_kernel<FWD, 15, MODE>;
     default: return nullptr;
   }
 }
@@ -356,12 +362,13 @@ static Kernel32 pick32_product(int logN) {
     case 12: return ntt32_product_kernel<12, MODE>;
     case 13: return ntt32_product_kernel<13, MODE>;
     case 14: return ntt32_product_kernel<14, MODE>;
+    case 15: return ntt32_product_kernel<15, MODE>;
     default: return nullptr;
   }
 }
 
 ntt_status launch_small(const Small32Launch& l) {
-  if (l.logN < 1 || l.logN > kMaxOnchipLog) return NTT_EINVAL_DEGREE;
+  if (l.logN < 1 || l.logN > kMaxSmallLog) return NTT_EINVAL_DEGREE;
   if (l.num_limbs == 0 || l.num_limbs > (uint32_t)kMaxPlansPerLaunch) return NTT_EINVAL_COUNT;
   Kernel32 k = nullptr;
   switch (l.op) {

@@ -1,4 +1,4 @@
-"""GPU parity of the word-size-2^32 path (moduli below 2^30, N <= 2^14) through the C ABI.
+"""GPU parity of the word-size-2^32 path (moduli below 2^30, N <= 2^15) through the C ABI.
 
 Forward lazy outputs must be the exact words of Algorithms 2 + 4 at beta = 2^32
 (the oracle's word-size model, itself pinned to the direct definition);
@@ -74,7 +74,7 @@ def _idx(N, seed, k=24):
     return np.unique(np.concatenate([r, np.array([0, 1, N // 2, N - 1], dtype=np.uint64)]))
 
 
-LOGNS = [1, 2, 3, 4, 5, 8, 10, 11, 12, 13, 14]
+LOGNS = [1, 2, 3, 4, 5, 8, 10, 11, 12, 13, 14, 15]
 
 
 @pytest.mark.parametrize("logN", LOGNS)
@@ -141,7 +141,7 @@ def test_round_trip32_in_place(nt):
     assert np.array_equal(host32(d), a)
 
 
-@pytest.mark.parametrize("logN", [1, 3, 6, 10, 12, 13, 14])
+@pytest.mark.parametrize("logN", [1, 3, 6, 10, 12, 13, 14, 15])
 def test_product32_against_schoolbook(nt, logN):
     N = 1 << logN
     moduli = _moduli(N, 3)
@@ -165,7 +165,7 @@ def test_product32_against_schoolbook(nt, logN):
                 assert np.array_equal(got[s][idx], oracle.negacyclic_mul_at(a[s], b[s], idx, q)), (p, l, q)
 
 
-@pytest.mark.parametrize("logN", [2, 10, 14])
+@pytest.mark.parametrize("logN", [2, 10, 14, 15])
 def test_product32_acc_with_lazy_multipliers(nt, logN):
     """acc += InvNTT(NTT(b) (.) m) with m crafted in [0, 4q) up to 4q - 1 (the input
     factor 4 of the multiply), against the oracle's transforms and element-wise product."""
