@@ -56,6 +56,7 @@ typedef int ntt_status;
 #define NTT_ENOTFOUND (-10)      /* unknown handle / nothing to report                 */
 #define NTT_EBUSY (-11)          /* admission refused: budget or queue full            */
 #define NTT_ETIMEDOUT (-12)      /* a wait ended before the awaited work completed     */
+#define NTT_ERANGE (-13)         /* validation mode: an operand value is out of range  */
 
 /* Largest ring degree and limb count the kernels are built for. */
 #define NTT_MAX_LOG_DEGREE 17
@@ -70,6 +71,19 @@ const char* ntt_status_string(ntt_status status);
 /* Releases every cached plan and library-owned device buffer.  Calls made
  * afterwards rebuild what they need.  Must not race with other calls. */
 ntt_status ntt_shutdown(void);
+
+/* Validation mode (a debugging aid).  Operand values outside the range a call
+ * states ([0, f q) for the call's input factor f, limb by limb) are a
+ * precondition violation: the output is unspecified and, by default, nothing
+ * checks them.  With validation on, every call that reads operand values first
+ * checks them on the device, waits for the stream, and returns NTT_ERANGE
+ * without launching the operation when one is out of range.  It is on when
+ * the environment variable NTT_VALIDATE is "1" at the first call, or after
+ * ntt_set_validate(1); ntt_set_validate(0) turns it off.  Not for timing or
+ * for calls captured into a graph (it synchronises the stream).  The batch
+ * calls check each item, ntt_server_submit checks a and b. */
+ntt_status ntt_set_validate(int on);
+int ntt_get_validate(void);
 
 /* ---------------------------------------------------------------------------
  * Plans: the paper's NTT object (Section 4, NTT class listing).  A plan owns

@@ -57,6 +57,8 @@ _SIGS = {
     "ntt_batch_autotune": (_ST, [_P, _P, ctypes.c_size_t, _P, ctypes.POINTER(ctypes.c_int)]),
     "eltwise_fma_mod": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _P]),
     "poly_mul_acc_ntt_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P, _P]),
+    "ntt_set_validate": (_ST, [ctypes.c_int]),
+    "ntt_get_validate": (ctypes.c_int, []),
     "ntt_forward_rns32": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _U64, _P]),
     "ntt_inverse_rns32": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _U64, _P]),
     "poly_mul_rns32": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P]),
@@ -96,12 +98,24 @@ NTT_EDEVICE = -8
 NTT_ENOMEM = -9
 NTT_ENOTFOUND = -10
 NTT_EBUSY = -11
+NTT_ETIMEDOUT = -12
+NTT_ERANGE = -13
 
 
 class NttError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
         super().__init__("%s failed: %s (%d)" % (what, status_string(status), status))
+
+
+def set_validate(on: bool):
+    """Validation mode: calls check operand ranges on the device and raise NttError
+    (status NTT_ERANGE) for out-of-range values.  A debugging aid: it synchronises."""
+    _check(_lib.ntt_set_validate(1 if on else 0), "ntt_set_validate")
+
+
+def get_validate() -> bool:
+    return bool(_lib.ntt_get_validate())
 
 
 def status_string(status: int) -> str:

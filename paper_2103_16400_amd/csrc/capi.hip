@@ -72,6 +72,11 @@ ntt_status ntt_rns(bool fwd, uint64_t* result, const uint64_t* operand, const ui
   std::vector<const ntt_plan*> plans;
   st = rns_plans(N, moduli, L, plans);
   if (st) return st;
+  if (validate_enabled()) {
+    st = check_range(operand, 64, N, moduli, L, B, in_f, (hipStream_t)stream);
+    if (!st && mul) st = check_range(mul, 64, N, moduli, L, B, fwd ? 4 : 1, (hipStream_t)stream);
+    if (st) return st;
+  }
   NttLaunch l{result, operand, mul, tmp, plans.data(), (uint32_t)L, B, (uint32_t)in_f, (uint32_t)out_f,
               (hipStream_t)stream};
   return fwd ? launch_forward(l) : launch_inverse(l);
@@ -79,7 +84,7 @@ ntt_status ntt_rns(bool fwd, uint64_t* result, const uint64_t* operand, const ui
 
 // Word-size-2^32 path: moduli below 2^30 (4q < 2^32), N in [2, 2^15].
 ntt_status small_call(uint32_t op, uint32_t* out, const uint32_t* in, const uint32_t* mul, uint64_t N,
-                      const uint64_t* moduli, uint64_t L, uint64_t B, ntt_stream_t stream) {
+                      const uint64_t* moduli, uint64_t L, uint64_t B, uint64_t in_f, ntt_stream_t stream) {
   if (!out || !in || !moduli) return NTT_EINVAL_POINTER;
   if (B == 0 || L == 0 || L > NTT_MAX_LIMBS) return NTT_EINVAL_COUNT;
   ntt_status st = validate_degree(N);
@@ -93,6 +98,12 @@ ntt_status small_call(uint32_t op, uint32_t* out, const uint32_t* in, const uint
   std::vector<const ntt_plan*> plans;
   st = rns_plans(N, moduli, L, plans);
   if (st) return st;
+  if (validate_enabled()) {
+    st = check_range(in, 32, N, moduli, L, B, in_f, (hipStream_t)stream);
+    if (!st && mul) st = check_range(mul, 32, N, moduli, L, B, 4, (hipStream_t)stream);
+    if (!st && op == kSmallProductAcc) st = check_range(out, 32, N, moduli, L, B, 1, (hipStream_t)stream);
+    if (st) return st;
+  }
   Small32Launch l{out, in, mul, plans.data(), (uint32_t)L, B, logN, op, (hipStream_t)stream};
   return launch_small(l);
 }
@@ -104,6 +115,12 @@ ntt_status product_rns(bool acc, uint64_t* out, const uint64_t* b, const uint64_
   std::vector<const ntt_plan*> plans;
   ntt_status st = rns_plans(N, moduli, L, plans);
   if (st) return st;
+  if (validate_enabled()) {
+    st = check_range(b, 64, N, moduli, L, B, 1, (hipStream_t)stream);
+    if (!st) st = check_range(m, 64, N, moduli, L, B, 4, (hipStream_t)stream);
+    if (!st && acc) st = check_range(out, 64, N, moduli, L, B, 1, (hipStream_t)stream);
+    if (st) return st;
+  }
   NttLaunch l{out, b, m, nullptr, plans.data(), (uint32_t)L, B, 1, 1, (hipStream_t)stream};
   return launch_product(l, acc);
 }
@@ -122,6 +139,11 @@ ntt_status elt_rns(bool mult, uint64_t* result, const uint64_t* a, const uint64_
   if (st) return st;
   st = check_alias(result, b, bytes);
   if (st) return st;
+  if (validate_enabled()) {
+    st = check_range(a, 64, N, moduli, L, B, mult ? in_f : 1, (hipStream_t)stream);
+    if (!st) st = check_range(b, 64, N, moduli, L, B, mult ? in_f : 1, (hipStream_t)stream);
+    if (st) return st;
+  }
   EltLaunch l{result, a, b, N, moduli, (uint32_t)L, B, (uint32_t)in_f, (hipStream_t)stream};
   return mult ? launch_eltwise_mult(l) : launch_eltwise_add(l);
 }
@@ -139,6 +161,11 @@ ntt_status fma_rns(uint64_t* result, const uint64_t* a, const uint64_t* scalars,
   if (st) return st;
   if (z) {
     st = check_alias(result, z, bytes);
+    if (st) return st;
+  }
+  if (validate_enabled()) {
+    st = check_range(a, 64, N, moduli, L, B, in_f, (hipStream_t)stream);
+    if (!st && z) st = check_range(z, 64, N, moduli, L, B, in_f, (hipStream_t)stream);
     if (st) return st;
   }
   EltLaunch l{result, a, z, N, moduli, (uint32_t)L, B, (uint32_t)in_f, (hipStream_t)stream, scalars};
@@ -159,6 +186,11 @@ ntt_status sub_rns(bool negate, uint64_t* result, const uint64_t* a, const uint6
   if (st) return st;
   if (!negate) {
     st = check_alias(result, b, bytes);
+    if (st) return st;
+  }
+  if (validate_enabled()) {
+    st = check_range(a, 64, N, moduli, L, B, 1, (hipStream_t)stream);
+    if (!st && !negate) st = check_range(b, 64, N, moduli, L, B, 1, (hipStream_t)stream);
     if (st) return st;
   }
   EltLaunch l{result, a, negate ? nullptr : b, N, moduli, (uint32_t)L, B, 1, (hipStream_t)stream, nullptr};
@@ -184,14 +216,23 @@ const char* ntt_status_string(ntt_status s) {
     case NTT_ENOTFOUND: return "not found";
     case NTT_EBUSY: return "busy: admission refused";
     case NTT_ETIMEDOUT: return "timed out";
+    case NTT_ERANGE: return "an operand value is outside [0, f q) (validation mode)";
     default: return "unknown status";
   }
 }
 
 ntt_status ntt_shutdown(void) {
   clear_plan_cache();
+  free_validate_buffers();
   return NTT_OK;
 }
+
+ntt_status ntt_set_validate(int on) {
+  set_validate(on != 0);
+  return NTT_OK;
+}
+
+int ntt_get_validate(void) { return validate_enabled() ? 1 : 0; }
 
 ntt_status ntt_plan_create(ntt_plan** plan, uint64_t N, uint64_t q, uint64_t root_of_unity) {
   return build_plan(plan, N, q, root_of_unity);
@@ -212,6 +253,8 @@ static ntt_status single_plan_call(bool fwd, const ntt_plan* plan, uint64_t* res
   ntt_status st = fwd ? check_fwd_factors(in_f, out_f) : check_inv_factors(in_f, out_f);
   if (st) return st;
   st = check_alias(result, operand, plan->N * sizeof(uint64_t));
+  if (st) return st;
+  st = check_range(operand, 64, plan->N, &plan->q, 1, 1, in_f, (hipStream_t)stream);
   if (st) return st;
   const ntt_plan* plans[1] = {plan};
   NttLaunch l{result, operand, nullptr, nullptr, plans, 1, 1, (uint32_t)in_f, (uint32_t)out_f, (hipStream_t)stream};
@@ -438,7 +481,7 @@ ntt_status ntt_forward_rns32(uint32_t* result, const uint32_t* operand, uint64_t
     if (st) return st;
   }
   return small_call(output_mod_factor == 1 ? kSmallForwardCanon : kSmallForwardLazy, result, operand, nullptr, N,
-                    moduli, num_limbs, num_polys, stream);
+                    moduli, num_limbs, num_polys, input_mod_factor, stream);
 }
 
 ntt_status ntt_inverse_rns32(uint32_t* result, const uint32_t* operand, uint64_t N, const uint64_t* moduli,
@@ -451,7 +494,7 @@ ntt_status ntt_inverse_rns32(uint32_t* result, const uint32_t* operand, uint64_t
     if (st) return st;
   }
   return small_call(output_mod_factor == 1 ? kSmallInverseCanon : kSmallInverseLazy, result, operand, nullptr, N,
-                    moduli, num_limbs, num_polys, stream);
+                    moduli, num_limbs, num_polys, input_mod_factor, stream);
 }
 
 ntt_status poly_mul_acc_ntt_rns32(uint32_t* acc, const uint32_t* a_ntt, const uint32_t* b, uint64_t N,
@@ -462,7 +505,7 @@ ntt_status poly_mul_acc_ntt_rns32(uint32_t* acc, const uint32_t* a_ntt, const ui
     const size_t bytes = (size_t)(num_polys * num_limbs * N * sizeof(uint32_t));
     if (overlaps(acc, bytes, a_ntt, bytes) || overlaps(acc, bytes, b, bytes)) return NTT_EALIAS;
   }
-  return small_call(kSmallProductAcc, acc, b, a_ntt, N, moduli, num_limbs, num_polys, stream);
+  return small_call(kSmallProductAcc, acc, b, a_ntt, N, moduli, num_limbs, num_polys, 1, stream);
 }
 
 ntt_status poly_mul_rns32(uint32_t* result, const uint32_t* a, const uint32_t* b, uint64_t N, const uint64_t* moduli,
@@ -475,9 +518,9 @@ ntt_status poly_mul_rns32(uint32_t* result, const uint32_t* a, const uint32_t* b
     if (st) return st;
   }
   // result <- NTT(a) in [0, 4q); then on chip: result <- InvNTT(NTT(b) (.) result), canonical
-  ntt_status st = small_call(kSmallForwardLazy, result, a, nullptr, N, moduli, num_limbs, num_polys, stream);
+  ntt_status st = small_call(kSmallForwardLazy, result, a, nullptr, N, moduli, num_limbs, num_polys, 1, stream);
   if (st) return st;
-  return small_call(kSmallProduct, result, b, result, N, moduli, num_limbs, num_polys, stream);
+  return small_call(kSmallProduct, result, b, result, N, moduli, num_limbs, num_polys, 1, stream);
 }
 
 ntt_status ntt_autotune(uint64_t N, const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,

@@ -166,4 +166,13 @@ struct Small32Launch {
 };
 ntt_status launch_small(const Small32Launch& l);
 
+// Opt-in range validation (validate.hip): with validation on, check_range returns
+// NTT_ERANGE when a value of limb l is not below factor * moduli[l]; it waits for
+// the stream.  Off (the default), it returns NTT_OK at once.
+bool validate_enabled();
+void set_validate(bool on);
+void free_validate_buffers();
+ntt_status check_range(const void* data, int bits, uint64_t n, const uint64_t* moduli, uint64_t num_limbs,
+                       uint64_t num_polys, uint64_t factor, hipStream_t stream);
+
 }  // namespace nttamd

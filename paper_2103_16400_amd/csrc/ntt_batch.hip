@@ -394,12 +394,28 @@ ntt_status ntt_batch_set_grid(ntt_batch* b, int workgroups) {
   return NTT_OK;
 }
 
+// Validation mode: each task's inputs against its range (forward and product
+// inputs below q, inverse inputs below 2q).
+static ntt_status check_items(const ntt_batch_item* items, size_t count, hipStream_t stream) {
+  if (!validate_enabled()) return NTT_OK;
+  for (size_t i = 0; i < count; ++i) {
+    const ntt_batch_item& it = items[i];
+    const bool inv = it.op == NTT_BATCH_INV_LAZY || it.op == NTT_BATCH_INV;
+    ntt_status st = check_range(it.in, 64, it.N, &it.q, 1, 1, inv ? 2 : 1, stream);
+    if (!st && it.op == NTT_BATCH_PRODUCT) st = check_range(it.in2, 64, it.N, &it.q, 1, 1, 1, stream);
+    if (st) return st;
+  }
+  return NTT_OK;
+}
+
 ntt_status ntt_batch_run(ntt_batch* b, const ntt_batch_item* items, size_t count, ntt_stream_t stream) {
   if (!b || (!items && count)) return NTT_EINVAL_POINTER;
   if (count > b->capacity) return NTT_EINVAL_COUNT;
   if (count == 0) return NTT_OK;
   size_t n = 0;
   ntt_status st = batch_prepare(b, items, count, &n);
+  if (st) return st;
+  st = check_items(items, count, (hipStream_t)stream);
   if (st) return st;
   return batch_launch_staged(b, n, (hipStream_t)stream, false);
 }
@@ -410,6 +426,8 @@ ntt_status ntt_batch_run_graph(ntt_batch* b, const ntt_batch_item* items, size_t
   if (count == 0) return NTT_OK;
   size_t n = 0;
   ntt_status st = batch_prepare(b, items, count, &n);
+  if (st) return st;
+  st = check_items(items, count, (hipStream_t)stream);
   if (st) return st;
   return batch_launch_staged(b, n, (hipStream_t)stream, true);
 }

@@ -617,6 +617,11 @@ ntt_status ntt_server_submit(ntt_server* s, const ntt_request* q, uint64_t* tick
     if (e) return reject(e);
     r->plans[l] = p;
   }
+  if (validate_enabled()) {
+    e = check_range(q->a, 64, q->N, q->moduli, q->num_limbs, 1, 1, nullptr);
+    if (!e) e = check_range(q->b, 64, q->N, q->moduli, q->num_limbs, 1, 1, nullptr);
+    if (e) return reject(e);
+  }
   std::lock_guard<std::mutex> g(s->mu);
   if (s->stop) {
     ++s->st.rejected;

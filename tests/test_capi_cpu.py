@@ -146,3 +146,15 @@ def test_small_modulus_validation_without_device(nt):
     assert L.poly_mul_acc_ntt_rns32(fake, other, shifted, 1024, small, 1, 1, None) == nt.NTT_EALIAS
     assert L.poly_mul_acc_ntt_rns32(fake, other, other, 1 << 16, small, 1, 1, None) == nt.NTT_EINVAL_DEGREE
     assert L.poly_mul_acc_ntt_rns32(fake, other, other, 1024, big, 1, 1, None) == nt.NTT_EINVAL_MODULUS
+
+
+def test_validation_toggle_without_device(nt):
+    """Validation mode is off by default, switches on and off, and has its own status."""
+    L = _raw(nt)
+    was = L.ntt_get_validate()
+    try:
+        assert L.ntt_set_validate(1) == nt.NTT_OK and L.ntt_get_validate() == 1
+        assert L.ntt_set_validate(0) == nt.NTT_OK and L.ntt_get_validate() == 0
+    finally:
+        L.ntt_set_validate(was)
+    assert nt.NTT_ERANGE == -13 and "outside" in nt.status_string(nt.NTT_ERANGE)
