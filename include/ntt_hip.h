@@ -360,6 +360,15 @@ ntt_status ntt_batch_run_graph(ntt_batch* batch, const ntt_batch_item* items, si
  * count in *chosen, may be NULL).  Runs the batch several times, so every
  * task must have out != in (NTT_EALIAS otherwise); outputs end up holding the
  * batch's result.  Synchronises `stream`. */
+/* One-shot batch calls: run a task list whose items are all forward
+ * (NTT_BATCH_FWD_LAZY / NTT_BATCH_FWD), all inverse (NTT_BATCH_INV_LAZY /
+ * NTT_BATCH_INV) or all products (NTT_BATCH_PRODUCT); NTT_EINVAL_FACTOR for
+ * an item of another kind.  They use a library-owned batch context per host
+ * thread and device (grown to the largest list seen, freed by ntt_shutdown)
+ * and replay its captured graph; otherwise as ntt_batch_run_graph. */
+ntt_status ntt_batch_forward(const ntt_batch_item* items, size_t count, ntt_stream_t stream);
+ntt_status ntt_batch_inverse(const ntt_batch_item* items, size_t count, ntt_stream_t stream);
+ntt_status ntt_batch_product(const ntt_batch_item* items, size_t count, ntt_stream_t stream);
 ntt_status ntt_batch_autotune(ntt_batch* batch, const ntt_batch_item* items, size_t count, ntt_stream_t stream,
                               int* chosen);
 

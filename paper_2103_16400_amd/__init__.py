@@ -57,6 +57,9 @@ _SIGS = {
     "ntt_batch_autotune": (_ST, [_P, _P, ctypes.c_size_t, _P, ctypes.POINTER(ctypes.c_int)]),
     "eltwise_fma_mod": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _P]),
     "poly_mul_acc_ntt_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P, _P]),
+    "ntt_batch_forward": (_ST, [_P, ctypes.c_size_t, _P]),
+    "ntt_batch_inverse": (_ST, [_P, ctypes.c_size_t, _P]),
+    "ntt_batch_product": (_ST, [_P, ctypes.c_size_t, _P]),
     "ntt_set_validate": (_ST, [ctypes.c_int]),
     "ntt_get_validate": (ctypes.c_int, []),
     "ntt_forward_rns32": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _U64, _P]),
@@ -334,6 +337,26 @@ class Batch:
             items, count = self.make_items(items)
         fn = _lib.ntt_batch_run_graph if graph else _lib.ntt_batch_run
         _check(fn(self._h, items, count, _stream(stream)), "ntt_batch_run_graph" if graph else "ntt_batch_run")
+
+
+def _oneshot(name, tasks, stream):
+    items, count = Batch.make_items(tasks)
+    _check(getattr(_lib, name)(ctypes.cast(items, _P), count, _stream(stream)), name)
+
+
+def batch_forward(tasks, stream=None):
+    """One-shot batch of forward tasks (op, out, in, in2, tmp, N, q), op BATCH_FWD_LAZY or BATCH_FWD."""
+    _oneshot("ntt_batch_forward", tasks, stream)
+
+
+def batch_inverse(tasks, stream=None):
+    """One-shot batch of inverse tasks, op BATCH_INV_LAZY or BATCH_INV."""
+    _oneshot("ntt_batch_inverse", tasks, stream)
+
+
+def batch_product(tasks, stream=None):
+    """One-shot batch of product tasks, op BATCH_PRODUCT."""
+    _oneshot("ntt_batch_product", tasks, stream)
 
 
 def poly_mul_acc_ntt_rns(acc, a_ntt, b, N, moduli, num_polys, workspace=None, stream=None):

@@ -222,6 +222,7 @@ const char* ntt_status_string(ntt_status s) {
 }
 
 ntt_status ntt_shutdown(void) {
+  free_oneshot_batches();
   clear_plan_cache();
   free_validate_buffers();
   return NTT_OK;

@@ -172,6 +172,10 @@ ntt_status launch_small(const Small32Launch& l);
 bool validate_enabled();
 void set_validate(bool on);
 void free_validate_buffers();
+// One-shot batch calls (ntt_batch.hip): per-thread contexts, freed by ntt_shutdown.
+ntt_status oneshot_run(const ntt_batch_item* items, size_t count, ntt_stream_t stream, uint32_t op_a,
+                       uint32_t op_b);
+void free_oneshot_batches();
 ntt_status check_range(const void* data, int bits, uint64_t n, const uint64_t* moduli, uint64_t num_limbs,
                        uint64_t num_polys, uint64_t factor, hipStream_t stream);
 

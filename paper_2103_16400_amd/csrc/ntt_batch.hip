@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -335,6 +336,50 @@ ntt_status batch_launch_tasks(ntt_batch* b, const BatchTask* tasks, size_t count
 
 using namespace nttamd;
 
+namespace nttamd {
+
+static std::mutex g_oneshot_mu;
+static std::map<std::pair<std::thread::id, int>, ntt_batch*> g_oneshot;
+
+// Runs items whose ops are op_a or op_b through the calling thread's context on
+// the current device, growing it (a new context of at least twice the size)
+// when the list does not fit.
+ntt_status oneshot_run(const ntt_batch_item* items, size_t count, ntt_stream_t stream, uint32_t op_a,
+                       uint32_t op_b) {
+  if (!items && count) return NTT_EINVAL_POINTER;
+  if (count == 0) return NTT_OK;
+  for (size_t i = 0; i < count; ++i)
+    if (items[i].op != op_a && items[i].op != op_b) return NTT_EINVAL_FACTOR;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return NTT_EDEVICE;
+  const auto key = std::make_pair(std::this_thread::get_id(), dev);
+  ntt_batch* b = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_oneshot_mu);
+    auto it = g_oneshot.find(key);
+    if (it != g_oneshot.end()) b = it->second;
+  }
+  if (!b || b->capacity < count) {
+    const size_t cap = b ? std::max(count, 2 * b->capacity) : std::max<size_t>(count, 1024);
+    ntt_batch* nb = nullptr;
+    ntt_status st = ntt_batch_create(&nb, cap);
+    if (st) return st;
+    if (b) (void)ntt_batch_destroy(b);          // waits for its launches in flight
+    std::lock_guard<std::mutex> lk(g_oneshot_mu);
+    g_oneshot[key] = nb;
+    b = nb;
+  }
+  return ntt_batch_run_graph(b, items, count, stream);
+}
+
+void free_oneshot_batches() {
+  std::lock_guard<std::mutex> lk(g_oneshot_mu);
+  for (auto& kv : g_oneshot) (void)ntt_batch_destroy(kv.second);
+  g_oneshot.clear();
+}
+
+}  // namespace nttamd
+
 extern "C" {
 
 static void release_stage(ntt_batch_stage& g) {
@@ -468,6 +513,19 @@ ntt_status ntt_batch_autotune(ntt_batch* b, const ntt_batch_item* items, size_t 
   st = ntt_batch_set_grid(b, best);
   if (chosen) *chosen = best;
   return st;
+}
+
+
+// One-shot batch calls: a library-owned context per (host thread, device),
+// grown to the largest task count seen, run through its captured graph.
+ntt_status ntt_batch_forward(const ntt_batch_item* items, size_t count, ntt_stream_t stream) {
+  return nttamd::oneshot_run(items, count, stream, NTT_BATCH_FWD_LAZY, NTT_BATCH_FWD);
+}
+ntt_status ntt_batch_inverse(const ntt_batch_item* items, size_t count, ntt_stream_t stream) {
+  return nttamd::oneshot_run(items, count, stream, NTT_BATCH_INV_LAZY, NTT_BATCH_INV);
+}
+ntt_status ntt_batch_product(const ntt_batch_item* items, size_t count, ntt_stream_t stream) {
+  return nttamd::oneshot_run(items, count, stream, NTT_BATCH_PRODUCT, NTT_BATCH_PRODUCT);
 }
 
 }  // extern "C"

@@ -644,6 +644,29 @@ def test_batch_graph_replays(nt):
     batch.close()
 
 
+def test_batch_one_shot_calls(nt):
+    """ntt_batch_forward / _inverse / _product: uneven task lists of one kind through the
+    library-owned per-thread context (grown past its first size), against the oracle;
+    a task of another kind is refused."""
+    serving = PRIMES["serving"]["moduli"]
+    for rnd, count in enumerate([30, 3000]):               # the second list outgrows the first context (1024)
+        base = [(10 + (k % 8), serving[(k * 7) % len(serving)]) for k in range(count)]
+        small = [(lg, q) for lg, q in base if lg <= 12] if count > 100 else base
+        for kind, ops, fn in [("fwd", [nt.BATCH_FWD_LAZY, nt.BATCH_FWD], nt.batch_forward),
+                              ("inv", [nt.BATCH_INV_LAZY, nt.BATCH_INV], nt.batch_inverse),
+                              ("prod", [nt.BATCH_PRODUCT], nt.batch_product)]:
+            specs = [(ops[k % len(ops)], lg, q) for k, (lg, q) in enumerate(small)]
+            tasks, host = _batch_case(nt, 120 + rnd, specs)
+            fn(tasks)
+            idx = list(range(0, len(tasks), max(1, len(tasks) // 24)))
+            _check_batch_outputs(nt, [tasks[i] for i in idx], [host[i] for i in idx])
+    d = empty_dev(1024)
+    q = PRIMES["single_1024"]["moduli"][0]
+    with pytest.raises(nt.NttError) as e:
+        nt.batch_forward([(nt.BATCH_INV, d, d, None, None, 1024, q)])
+    assert e.value.status == nt.NTT_EINVAL_FACTOR
+
+
 def test_batch_rejects_bad_items(nt):
     batch = nt.Batch(4)
     d = empty_dev(1024)
