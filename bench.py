@@ -358,6 +358,29 @@ def time_small_primes(nt, torch, primes, key="small_16384", B=512, steps=100, wa
             "fwd_limb_ntts_per_s": round(limbs / (fwd_ms * 1e-3), 1)}
 
 
+def time_copy(torch, words=1 << 27, reps=10):
+    """Achieved streaming rate of a plain 1 GiB device-to-device copy (bytes read + written / time):
+    the practical HBM ceiling beside the 8 TB/s peak."""
+    src = torch.ones(words, dtype=torch.int64, device="cuda:0")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = 2 * words * 8 / (ms * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_moved": 2 * words * 8, "ms": round(ms, 4), "gbs": round(gbs, 1),
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def time_single_1024(nt, torch, primes, reps=200):
     """Per-call latency of one forward and one inverse NTT at N = 1024 (single limb)."""
     p1 = primes["single_1024"]
@@ -466,8 +489,14 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
-    fwd_ms = float(np.mean([es[0].elapsed_time(es[1]) for es in ev]))
-    prod_ms = float(np.mean([es[1].elapsed_time(es[2]) for es in ev]))
+    fwd_all = np.array([es[0].elapsed_time(es[1]) for es in ev])
+    prod_all = np.array([es[1].elapsed_time(es[2]) for es in ev])
+    step_all = np.array([es[0].elapsed_time(es[2]) for es in ev])
+    fwd_ms = float(fwd_all.mean())
+    prod_ms = float(prod_all.mean())
+
+    def pct(x):
+        return [round(float(v), 4) for v in np.percentile(x, [10, 50, 90])]
 
     limbs = B * L
     fwd_per_step = 2 * limbs
@@ -507,12 +536,15 @@ def main():
         "roofline_fwd": roof("forward", "ntt_onchip_kernel<fwd, N=2^14>: forward NTT of %d limbs, one launch"
                              % limbs, fwd_bytes, fwd_ms),
         "step_kernels_ms": {"fwd_lazy": round(fwd_ms, 4), "fwd_mul_inv_acc_fused": round(prod_ms, 4)},
+        "p10_p50_p90_ms": {"step_events": pct(step_all), "fwd_lazy": pct(fwd_all),
+                           "fwd_mul_inv_acc_fused": pct(prod_all)},
         "fwd_ntt_rate": round(limbs / (fwd_ms * 1e-3), 1),
         "products_per_s": round(limbs / (wall / args.steps), 1),
     }
     if not args.no_extra:
         del a, b, c, ws, acc
         torch.cuda.empty_cache()
+        out["hbm_copy"] = time_copy(torch)
         out["large_ring_n65536_l32"] = time_large_ring(nt, torch, load_primes())
         out["single_n1024"] = time_single_1024(nt, torch, load_primes())
         out["small_primes_n16384_l8"] = time_small_primes(nt, torch, load_primes())
