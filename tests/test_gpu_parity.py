@@ -183,6 +183,27 @@ def test_forward_inverse_small(nt, logN):
         assert np.array_equal(from_dev(d2), a)
 
 
+@pytest.mark.parametrize("logN", [10, 14, 16])
+def test_transform_words_across_modulus_sizes(nt, logN):
+    """Every modulus size Q = 30..62 (the smallest Q-bit prime = 1 mod 2^18), through the
+    on-chip (2^10), split-exchange on-chip (2^14) and two-pass (2^16) kernels: the forward's
+    lazy words equal the Harvey model in full, and the inverse's canonical output equals the
+    model's (itself pinned to the definition)."""
+    N = 1 << logN
+    for Q in range(30, 63):
+        q = _edge(Q)
+        psi = oracle.min_root(N, q)
+        a = lazy_mod(unit_seed(24, logN, Q), N, q, 4)
+        a[-1] = np.uint64(4 * q - 1)
+        dout = empty_dev(N)
+        nt.ntt_forward(dout, to_dev(a), N, q, 4, 4)
+        assert np.array_equal(from_dev(dout), oracle.harvey_forward(a, q, psi, 4)), Q
+        A = lazy_mod(unit_seed(25, logN, Q), N, q, 2)
+        A[0] = np.uint64(2 * q - 1)
+        nt.ntt_inverse(dout, to_dev(A), N, q, 2, 1)
+        assert np.array_equal(from_dev(dout), oracle.harvey_inverse(A, q, psi, 1)), Q
+
+
 @pytest.mark.parametrize("logN", [14, 15, 16, 17])
 def test_forward_inverse_multipass(nt, logN):
     N = 1 << logN
