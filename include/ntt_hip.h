@@ -373,13 +373,15 @@ ntt_status ntt_batch_autotune(ntt_batch* batch, const ntt_batch_item* items, siz
                               int* chosen);
 
 /* ---------------------------------------------------------------------------
- * Autotuning (the paper's Section 4 remark that the best implementation could
- * be chosen by "a small number of trials" at initialisation).  For two-pass
- * sizes (N > 2^14) the library has several kernel variants per pass; this call
- * times each on a scratch buffer of num_limbs * num_polys * N words (allocated
- * and freed here, so it is not a hot-path call), synchronises `stream`, and
- * uses the fastest for later calls of the same direction, N and batch-size
- * class (up to 64 limbs, or more).  choice_fwd / choice_inv (may be NULL)
+ * Autotuning (Section 4 notes that the best implementation can be picked by
+ * trying the candidates at initialisation).  For two-pass sizes (N > 2^14) the
+ * library has several kernel variants per pass; this call times each, 20
+ * launches per variant, on scratch operand sets of num_limbs * num_polys * N
+ * words used in turn (enough sets, up to 32, that they exceed the 256 MB MALL,
+ * so the data comes from HBM as in a streaming workload; allocated and freed
+ * here, so it is not a hot-path call), synchronises `stream`, and uses the
+ * fastest for later calls of the same direction, N and batch-size class (up to
+ * 64 limbs, or more).  choice_fwd / choice_inv (may be NULL)
  * receive the chosen variant indices.  N <= 2^14 has a single variant.
  * ntt_set_variant pins a variant explicitly (forward != 0 for the forward
  * transform); NTT_EINVAL_COUNT for an unknown variant.

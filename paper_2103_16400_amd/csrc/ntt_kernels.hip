@@ -37,18 +37,21 @@ namespace nttamd {
 
 // LASTPASS: this pass produces the transform's output (output mode MODE and,
 // for the inverse, the fused N^{-1} stage); PTOP: highest stage bit read from
-// the transposed sub-tables in the low pass (-1: none).
-template <bool FWD, int LOGT, int LOGR, int LOGC, int LOGH, int MINW, int MODE, bool LASTPASS, int PTOP>
+// the transposed sub-tables in the low pass (-1: none); HAND: hand-scheduled
+// butterflies (which need a 128-VGPR budget) or the plain C++ ones.
+template <bool FWD, int LOGT, int LOGR, int LOGC, int LOGH, int MINW, int MODE, bool LASTPASS, int PTOP,
+          bool HAND = true>
 __global__ void __launch_bounds__((1 << (LOGT + LOGH + LOGC)) >> LOGR, MINW) ntt_tile_kernel(const PassArgs a) {
-  static_assert(MINW <= 4, "the butterflies use v122..v127: keep a budget of at least 128 VGPRs");
-  using K = TileNtt<FWD, LOGT, LOGR, LOGC, LOGH>;
+  static_assert(!HAND || MINW <= 4, "the butterflies use v122..v127: keep a budget of at least 128 VGPRs");
+  using K = TileNtt<FWD, LOGT, LOGR, LOGC, LOGH, HAND>;
   __shared__ u64 lds[K::LDSW];
   const u32 item = a.item0 + blockIdx.y;
   const u32 logN = a.logN;
   const PlanView pv = load_plan(a.plan[item % a.num_limbs], FWD, 1ull << logN);
   const u64 base = (u64)item << logN;
-  tile_body<FWD, LOGT, LOGR, LOGC, LOGH, MODE, LASTPASS, PTOP>(pv, logN, a.b0, blockIdx.x, a.in + base, a.out + base,
-                                                              a.mul ? a.mul + base : nullptr, lds, true);
+  tile_body<FWD, LOGT, LOGR, LOGC, LOGH, MODE, LASTPASS, PTOP, HAND>(pv, logN, a.b0, blockIdx.x, a.in + base,
+                                                                    a.out + base, a.mul ? a.mul + base : nullptr, lds,
+                                                                    true);
 }
 
 // ---- schedules ---------------------------------------------------------------
@@ -56,28 +59,34 @@ __global__ void __launch_bounds__((1 << (LOGT + LOGH + LOGC)) >> LOGR, MINW) ntt
 typedef void (*PassKernel)(const PassArgs);
 
 // Schedule variants: (log2 coefficients per thread of the high pass, of the
-// low pass).  Fewer coefficients per thread means more waves per tile, which
-// hides more latency when the batch is small, at the price of more LDS rounds.
-// The low pass reads the plan's transposed sub-tables only with 2^kMpLogrLo
-// coefficients per thread (the layout they are built for); otherwise it reads
-// the natural table.
-constexpr int kVariants = 5;
-struct VariantShape { int hi, lo; };
-static constexpr VariantShape kVariantShape[kVariants] = {{4, 4}, {3, 4}, {2, 4}, {3, 3}, {2, 3}};
+// low pass, butterflies).  Fewer coefficients per thread means more waves per
+// tile, which hides more latency when the batch is small, at the price of more
+// LDS rounds.  The low pass reads the plan's transposed sub-tables only with
+// 2^kMpLogrLo coefficients per thread (the layout they are built for);
+// otherwise it reads the natural table.  The last variant uses the plain C++
+// butterflies, which need no fixed registers: with 4 coefficients per thread
+// it fits 64 VGPRs, so twice as many waves share a CU (more latency hidden, at
+// about 30% more VALU per butterfly).
+constexpr int kVariants = 6;
+struct VariantShape { int hi, lo; bool hand; };
+static constexpr VariantShape kVariantShape[kVariants] = {{4, 4, true}, {3, 4, true}, {2, 4, true},
+                                                          {3, 3, true}, {2, 3, true}, {2, 2, false}};
 // At most 1024 threads per workgroup: 2^(tile bits + 4 columns - log2 R).
 __host__ __device__ constexpr int hi_logr_clamped(int lt_hi, int logr) { return lt_hi + 4 - logr > 10 ? lt_hi - 6 : logr; }
 static int hi_logr(int logN, int variant) { return hi_logr_clamped(mp_logt_hi(logN), kVariantShape[variant].hi); }
 static int lo_logr(int variant) { return kVariantShape[variant].lo; }
 
-template <bool FWD, int LOGN, int MODE, bool LAST, int LOGR0>
+template <bool FWD, int LOGN, int MODE, bool LAST, int LOGR0, bool HAND = true>
 static PassKernel pick_hi_r() {
   constexpr int LT = mp_logt_hi(LOGN);
   constexpr int LOGR = hi_logr_clamped(LT, LOGR0);
-  constexpr int MW = LOGR >= 4 && LT >= 9 ? 2 : 4;   // at least 128 VGPRs: the butterflies use v122..v127
-  return ntt_tile_kernel<FWD, LT, LOGR, 4, 0, MW, MODE, LAST, -1>;
+  // hand-scheduled butterflies: at least 128 VGPRs (they use v122..v127); C++ ones: 64
+  constexpr int MW = !HAND ? 8 : (LOGR >= 4 && LT >= 9 ? 2 : 4);
+  return ntt_tile_kernel<FWD, LT, LOGR, 4, 0, MW, MODE, LAST, -1, HAND>;
 }
 template <bool FWD, int LOGN, int MODE, bool LAST>
 static PassKernel pick_hi(int variant) {
+  if (!kVariantShape[variant].hand) return pick_hi_r<FWD, LOGN, MODE, LAST, 2, false>();
   switch (kVariantShape[variant].hi) {
     case 4: return pick_hi_r<FWD, LOGN, MODE, LAST, 4>();
     case 3: return pick_hi_r<FWD, LOGN, MODE, LAST, 3>();
@@ -89,6 +98,7 @@ static PassKernel pick_lo(int variant) {
   constexpr int LT = mp_logt_lo(LOGN);
   constexpr int LH = 12 - LT;                          // 4096-coefficient tiles
   if (lo_logr(variant) == kMpLogrLo) return ntt_tile_kernel<FWD, LT, kMpLogrLo, 0, LH, 4, MODE, LAST, mp_perm_top(FWD, LOGN)>;
+  if (!kVariantShape[variant].hand) return ntt_tile_kernel<FWD, LT, 2, 0, LH, 8, MODE, LAST, -1, false>;
   return ntt_tile_kernel<FWD, LT, 3, 0, LH, 4, MODE, LAST, -1>;
 }
 
