@@ -43,10 +43,10 @@ HBM_PEAK_GBS = 8000.0
 # Valid only for the kernel sources they were taken with, identified by the SHA-256 of these files.
 COUNTERS_N16384 = {
     "sources": ["ntt_onchip.hip", "ntt_onchip.h", "ntt_common.h", "modarith.h", "internal.h"],
-    "sha256": "88b148b5b5e63bba453d0c039cef1270ccb4e21cf0b2ef885b590f493dc827f2",
+    "sha256": "502f0621b02dcd193aca81ace3de7928f4bd31fb37489090ca9a78dee94adbc0",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "product": {"fetch_kib": 831361.8, "write_kib": 540672.0, "valu_insts": 427556864},
-    "forward": {"fetch_kib": 275904.7, "write_kib": 524288.4, "valu_insts": 175996928},
+    "product": {"fetch_kib": 832664.5, "write_kib": 540672.0, "valu_insts": 427556864},
+    "forward": {"fetch_kib": 275435.0, "write_kib": 524288.2, "valu_insts": 175996928},
 }
 
 # VALU issue capacity: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at 2.4 GHz
