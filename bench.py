@@ -116,23 +116,26 @@ def cpu_baseline(N, moduli, psis, budget_s=12.0):
 def time_large_ring(nt, torch, primes, reps=20):
     """Forward and inverse NTT of 32-limb polynomials at N = 2^16 (60-bit primes), one
     launch sequence per batch of B polynomials, rotating over 16 distinct polynomials
-    (256 MiB) so coefficients come from HBM rather than the 256 MB MALL."""
+    (256 MiB) so coefficients come from HBM rather than the 256 MB MALL.  Out of place, into
+    an output pool of the same size, so every call reads canonical inputs (factor 1) and
+    its writes rotate through HBM as well."""
     p3 = primes["large_65536"]
     N, moduli = p3["N"], p3["moduli"]
     L = len(moduli)
     pool = 16
     dev = torch.device("cuda:0")
     data = torch.from_numpy(gen_operand(3, N, moduli, pool).view(np.int64)).to(dev)
-    ws = torch.empty(8 * L * N, dtype=torch.int64, device=dev)
+    dst = torch.empty_like(data)
     stream = torch.cuda.current_stream()
     out = {}
     for B in (1, 2, 8):
-        views = [data[i * L * N:(i + B) * L * N] for i in range(0, pool - B + 1, B)]
+        views = [(data[i * L * N:(i + B) * L * N], dst[i * L * N:(i + B) * L * N])
+                 for i in range(0, pool - B + 1, B)]
         res = {}
         res["autotune_variant_fwd_inv"] = list(nt.autotune(N, moduli, B, stream=stream))
-        for name, fn in (("fwd", lambda v: nt.ntt_forward_rns(v, v, N, moduli, B, 1, 4, stream=stream)),
-                         ("fwd_canon", lambda v: nt.ntt_forward_rns(v, v, N, moduli, B, 1, 1, stream=stream)),
-                         ("inv", lambda v: nt.ntt_inverse_rns(v, v, N, moduli, B, 1, 2, stream=stream))):
+        for name, fn in (("fwd", lambda v: nt.ntt_forward_rns(v[1], v[0], N, moduli, B, 1, 4, stream=stream)),
+                         ("fwd_canon", lambda v: nt.ntt_forward_rns(v[1], v[0], N, moduli, B, 1, 1, stream=stream)),
+                         ("inv", lambda v: nt.ntt_inverse_rns(v[1], v[0], N, moduli, B, 1, 2, stream=stream))):
             for v in views[:2]:
                 fn(v)
             torch.cuda.synchronize()
