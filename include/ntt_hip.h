@@ -85,6 +85,22 @@ ntt_status ntt_shutdown(void);
 ntt_status ntt_set_validate(int on);
 int ntt_get_validate(void);
 
+/* Wide-range butterflies (on by default).  For N <= 2^14 and launches whose
+ * moduli are all below 2^58, the transforms (and the fused products built on
+ * them) use a cheaper form of the butterflies of Algorithms 4 and 5: the
+ * Shoup quotient omits its lowest partial product (so it may be one short and
+ * W X mod q is left in [0, 3q)), and the forward lets values grow by up to 3q
+ * a stage instead of reducing them to [0, 2q), with one reduction after the
+ * last stage.  Values stay below 2^64 because q < 2^58.  Canonical outputs are
+ * identical either way; lazy outputs stay within the stated ranges and
+ * congruent mod q but are not always the words Algorithms 4 and 5 produce.
+ * ntt_set_wide_range(0) makes every kernel use the paper's butterflies (for
+ * example, to reproduce its lazy words); it applies to calls enqueued
+ * afterwards and must not race with them.  The batch calls, the server and
+ * the multi-pass sizes (N >= 2^15) always use the paper's butterflies. */
+ntt_status ntt_set_wide_range(int on);
+int ntt_get_wide_range(void);
+
 /* ---------------------------------------------------------------------------
  * Plans: the paper's NTT object (Section 4, NTT class listing).  A plan owns
  * the device-resident tables of one (N, q, psi): psi_rev[k] = psi^brv(k) and
@@ -118,6 +134,9 @@ uint64_t ntt_plan_root(const ntt_plan* plan);
  *                      (lazy: congruent to the canonical value mod q)
  * ntt_forward uses the plan of (N, q, smallest psi) from the library cache;
  * ntt_forward_plan uses an explicit plan.
+ * Lazy results are the exact words of Algorithm 4 except where the wide-range
+ * butterflies run (see ntt_set_wide_range): then they are other values of the
+ * same residue within the same range.
  */
 ntt_status ntt_forward(uint64_t* result, const uint64_t* operand, uint64_t N, uint64_t q,
                        uint64_t input_mod_factor, uint64_t output_mod_factor, ntt_stream_t stream);

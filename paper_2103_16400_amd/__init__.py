@@ -62,6 +62,8 @@ _SIGS = {
     "ntt_batch_product": (_ST, [_P, ctypes.c_size_t, _P]),
     "ntt_set_validate": (_ST, [ctypes.c_int]),
     "ntt_get_validate": (ctypes.c_int, []),
+    "ntt_set_wide_range": (_ST, [ctypes.c_int]),
+    "ntt_get_wide_range": (ctypes.c_int, []),
     "ntt_forward_rns32": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _U64, _P]),
     "ntt_inverse_rns32": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _U64, _P]),
     "poly_mul_rns32": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P]),
@@ -119,6 +121,16 @@ def set_validate(on: bool):
 
 def get_validate() -> bool:
     return bool(_lib.ntt_get_validate())
+
+
+def set_wide_range(on: bool):
+    """Wide-range butterflies for N <= 2^14 and moduli below 2^58 (on by default);
+    off: every kernel produces the lazy words of Algorithms 4 and 5."""
+    _check(_lib.ntt_set_wide_range(1 if on else 0), "ntt_set_wide_range")
+
+
+def get_wide_range() -> bool:
+    return bool(_lib.ntt_get_wide_range())
 
 
 def status_string(status: int) -> str:

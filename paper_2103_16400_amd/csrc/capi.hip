@@ -235,6 +235,13 @@ ntt_status ntt_set_validate(int on) {
 
 int ntt_get_validate(void) { return validate_enabled() ? 1 : 0; }
 
+ntt_status ntt_set_wide_range(int on) {
+  set_wide_range(on != 0);
+  return NTT_OK;
+}
+
+int ntt_get_wide_range(void) { return wide_range_enabled() ? 1 : 0; }
+
 ntt_status ntt_plan_create(ntt_plan** plan, uint64_t N, uint64_t q, uint64_t root_of_unity) {
   return build_plan(plan, N, q, root_of_unity);
 }

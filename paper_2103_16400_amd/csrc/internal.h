@@ -178,5 +178,10 @@ ntt_status oneshot_run(const ntt_batch_item* items, size_t count, ntt_stream_t s
 void free_oneshot_batches();
 ntt_status check_range(const void* data, int bits, uint64_t n, const uint64_t* moduli, uint64_t num_limbs,
                        uint64_t num_polys, uint64_t factor, hipStream_t stream);
+// Wide-range butterflies in the single-pass kernels (ntt_kernels.hip): used for
+// launches whose moduli are all below kWideModulusBound while enabled (the default).
+constexpr uint64_t kWideModulusBound = 1ull << 58;
+bool wide_range_enabled();
+void set_wide_range(bool on);
 
 }  // namespace nttamd

@@ -239,6 +239,157 @@ __device__ __forceinline__ void harvey_inv_last(u64& x0, u64& x1, u64 ni, u64 ni
       : NTTAMD_CLOBBERS);
 }
 
+// ---- Wide-range variants (moduli below 2^58, single-pass kernels) ----------
+//
+// Same butterflies with two changes that trade the paper's tight output ranges
+// for fewer instructions, valid while every value stays below 2^64:
+//   - the Shoup quotient is taken without the low partial product
+//     lo(W') lo(X), whose carry into the high word is at most 1.  The estimate
+//     Q' is then Q or Q - 1, so T = W X - Q' q lies in [0, 3q) (the bound
+//     [0, 2q) of the exact quotient, plus q) for every X < 2^64;
+//   - the forward skips the reduction of X0 to [0, 2q):
+//     X0 <- X0 + T, X1 <- X0 + 3q - T, so both grow by less than 3q a stage.
+// From inputs below f q, after s forward stages every value is below
+// (f + 3 s) q: 46 q < 2^64 for f = 4, s = 14 and q < 2^58.  The inverse keeps
+// its values in [0, 4q) (one conditional subtraction of 4q per sum), its
+// products in [0, 3q).  Outputs are congruent to the paper's mod q; the last
+// step of a transform brings them into the paper's output ranges.
+
+// Forward butterfly, wide range: X0 <- X0 + T, X1 <- X0 + 3q - T with
+// T = W X1 mod q in [0, 3q).  q3 = 3q, nq = 2^64 - q.
+__device__ __forceinline__ void harvey_fwd_wide(u64& x0, u64& x1, u64 w, u64 wp, u64 q3, u64 nq) {
+  u64 c, j, b, y0;
+  u32 y1l, y1h;
+  asm volatile("v_mad_u64_u32 v[124:125], %[j], %[pl], %[x1h], 0\n\t"        // P = lo(W') hi(X1) ...
+      "v_mad_u64_u32 v[124:125], %[c], %[ph], %[x1l], v[124:125]\n\t" // + hi(W') lo(X1), carry c
+      "v_mad_u64_u32 v[126:127], %[j], %[wl], %[x1l], 0\n\t"        // T = W X1 (low products)
+      "v_mov_b32 v124, v125\n\t"
+      "v_addc_co_u32 v125, %[j], 0, 0, %[c]\n\t"
+      "v_mad_u64_u32 v[124:125], %[j], %[ph], %[x1h], v[124:125]\n\t" // ... Q' = P >> 32 + hi(W') hi(X1)
+      "v_mad_u64_u32 v[126:127], %[j], v124, %[nql], v[126:127]\n\t"  // T += Q'0 nq0
+      "v_mul_lo_u32 v124, v124, %[nqh]\n\t"                          // cross products (high word only)
+      "v_mul_lo_u32 v125, v125, %[nql]\n\t"
+      "v_add3_u32 v127, v127, v124, v125\n\t"
+      "v_mul_lo_u32 v124, %[wl], %[x1h]\n\t"
+      "v_mul_lo_u32 v125, %[wh], %[x1l]\n\t"
+      "v_add3_u32 v127, v127, v124, v125\n\t"                        // T = W X1 mod q in [0, 3q)
+      "v_lshl_add_u64 v[124:125], %[x0], 0, %[q3]\n\t"               // x0 + 3q
+      "v_sub_co_u32 %[y1l], %[b], v124, v126\n\t"
+      "v_lshl_add_u64 %[y0], %[x0], 0, v[126:127]\n\t"               // X0 = x0 + T
+      "s_nop 0\n\t"
+      "v_subb_co_u32 %[y1h], %[b], v125, v127, %[b]"                 // X1 = x0 + 3q - T
+      : [y0] "=v"(y0), [y1l] "=&v"(y1l), [y1h] "=v"(y1h), [c] "=&s"(c), [j] "=&s"(j), [b] "=&s"(b)
+      : [x0] "v"(x0), [x1l] "v"(lo32(x1)), [x1h] "v"(hi32(x1)), [wl] "v"(lo32(w)), [wh] "v"(hi32(w)),
+        [pl] "v"(lo32(wp)), [ph] "v"(hi32(wp)), [q3] "s"(q3), [nql] "s"(lo32(nq)), [nqh] "s"(hi32(nq))
+      : "v124", "v125", "v126", "v127");
+  x0 = y0;
+  x1 = ((u64)y1h << 32) | y1l;
+}
+
+// Inverse butterfly, wide range, inputs in [0, 4q): X0 <- (X0 + X1) reduced
+// once by 4q, in [0, 4q); X1 <- W (X0 + 4q - X1) mod q in [0, 3q).
+// q4 = 4q, nq4 = 2^64 - 4q.
+__device__ __forceinline__ void harvey_inv_wide(u64& x0, u64& x1, u64 w, u64 wp, u64 q4, u64 nq, u64 nq4) {
+  u64 k, c, j, b, y1;
+  u32 y0l, y0h;
+  asm volatile("v_lshl_add_u64 v[124:125], %[x0], 0, %[q4]\n\t"              // x0 + 4q
+      "v_lshl_add_u64 v[126:127], %[x0], 0, %[x1]\n\t"              // S = x0 + x1 < 8q
+      "v_sub_co_u32 v124, %[b], v124, %[x1l]\n\t"
+      "v_cmp_le_u64 %[k], %[q4], v[126:127]\n\t"                    // S >= 4q
+      "v_lshl_add_u64 v[122:123], v[126:127], 0, %[nq4]\n\t"        // S - 4q
+      "v_subb_co_u32 v125, %[b], v125, %[x1h], %[b]\n\t"            // D = x0 + 4q - x1 < 8q
+      "v_cndmask_b32 %[y0l], v126, v122, %[k]\n\t"
+      "v_cndmask_b32 %[y0h], v127, v123, %[k]\n\t"                  // X0 in [0, 4q)
+      "v_mad_u64_u32 v[122:123], %[j], %[pl], v125, 0\n\t"          // P = lo(W') hi(D) ...
+      "v_mad_u64_u32 v[122:123], %[c], %[ph], v124, v[122:123]\n\t" // + hi(W') lo(D), carry c
+      "v_mad_u64_u32 v[126:127], %[j], %[wh], v124, 0\n\t"          // M = cross products
+      "v_mov_b32 v122, v123\n\t"
+      "v_addc_co_u32 v123, %[j], 0, 0, %[c]\n\t"
+      "v_mad_u64_u32 v[122:123], %[j], %[ph], v125, v[122:123]\n\t" // ... P = Q'
+      "v_mad_u64_u32 v[126:127], %[j], %[wl], v125, v[126:127]\n\t"
+      "v_mad_u64_u32 v[124:125], %[j], %[wl], v124, 0\n\t"          // T = W D (low products); D dies
+      "v_mad_u64_u32 v[124:125], %[j], v122, %[nql], v[124:125]\n\t"
+      "v_mad_u64_u32 v[126:127], %[j], v122, %[nqh], v[126:127]\n\t"
+      "v_mad_u64_u32 v[126:127], %[j], v123, %[nql], v[126:127]\n\t"
+      "v_lshlrev_b64 v[126:127], 32, v[126:127]\n\t"
+      "v_lshl_add_u64 %[y1], v[124:125], 0, v[126:127]"              // X1 = W D mod q in [0, 3q)
+      : [y0l] "=&v"(y0l), [y0h] "=&v"(y0h), [y1] "=v"(y1), [k] "=&s"(k), [c] "=&s"(c), [j] "=&s"(j),
+        [b] "=&s"(b)
+      : [x0] "v"(x0), [x1] "v"(x1), [x1l] "v"(lo32(x1)), [x1h] "v"(hi32(x1)), [wl] "v"(lo32(w)), [wh] "v"(hi32(w)),
+        [pl] "v"(lo32(wp)), [ph] "v"(hi32(wp)), [q4] "s"(q4), [nq4] "s"(nq4), [nql] "s"(lo32(nq)),
+        [nqh] "s"(hi32(nq))
+      : NTTAMD_CLOBBERS);
+  x0 = ((u64)y0h << 32) | y0l;
+  x1 = y1;
+}
+
+// Last inverse stage with N^{-1}, wide range, inputs in [0, 4q):
+// X0 <- N^{-1} (X0 + X1), X1 <- (W N^{-1}) (X0 + 4q - X1), both in [0, 3q).
+__device__ __forceinline__ void harvey_inv_last_wide(u64& x0, u64& x1, u64 ni, u64 nip, u64 wn, u64 wnp,
+                                                     u64 q4, u64 nq) {
+  u64 c, j, b;
+  asm volatile("v_lshl_add_u64 v[126:127], %[x1], 0, 0\n\t"                  // M = x1
+      "v_lshl_add_u64 v[124:125], %[x0], 0, %[q4]\n\t"              // x0 + 4q
+      "v_lshl_add_u64 v[122:123], %[x0], 0, %[x1]\n\t"              // P = S = x0 + x1 < 8q
+      "v_sub_co_u32 v124, %[b], v124, v126\n\t"
+      "v_mad_u64_u32 %[x0], %[j], %[nil], v122, 0\n\t"              // X0 = N^-1 S (low products) ...
+      "v_mad_u64_u32 %[x1], %[j], %[nih], v122, 0\n\t"              // X1 = its cross products
+      "v_subb_co_u32 v125, %[b], v125, v127, %[b]\n\t"              // T = D = x0 + 4q - x1 < 8q
+      "v_mad_u64_u32 %[x1], %[j], %[nil], v123, %[x1]\n\t"
+      "v_mad_u64_u32 v[126:127], %[j], %[npl], v123, 0\n\t"         // M = Q' for (N^-1', S) ...
+      "v_mad_u64_u32 v[126:127], %[c], %[nph], v122, v[126:127]\n\t"
+      "v_mov_b32 v126, v127\n\t"
+      "s_nop 0\n\t"
+      "v_addc_co_u32 v127, %[j], 0, 0, %[c]\n\t"
+      "v_mad_u64_u32 v[126:127], %[j], %[nph], v123, v[126:127]\n\t" // ... M = Q'
+      "v_mad_u64_u32 %[x0], %[j], v126, %[nql], %[x0]\n\t"
+      "v_mad_u64_u32 %[x1], %[j], v126, %[nqh], %[x1]\n\t"
+      "v_mad_u64_u32 %[x1], %[j], v127, %[nql], %[x1]\n\t"
+      "v_lshlrev_b64 %[x1], 32, %[x1]\n\t"
+      "v_lshl_add_u64 %[x0], %[x0], 0, %[x1]\n\t"                   // X0 = N^-1 S mod q in [0, 3q)
+      "v_mad_u64_u32 v[122:123], %[j], %[wpl], v125, 0\n\t"         // P = Q' for ((W N^-1)', D) ...
+      "v_mad_u64_u32 v[122:123], %[c], %[wph], v124, v[122:123]\n\t"
+      "v_mad_u64_u32 %[x1], %[j], %[wnl], v124, 0\n\t"              // X1 = W N^-1 D (low products)
+      "v_mov_b32 v122, v123\n\t"
+      "v_addc_co_u32 v123, %[j], 0, 0, %[c]\n\t"
+      "v_mad_u64_u32 v[122:123], %[j], %[wph], v125, v[122:123]\n\t" // ... P = Q'
+      "v_mad_u64_u32 v[126:127], %[j], %[wnh], v124, 0\n\t"         // M = cross products
+      "v_mad_u64_u32 v[126:127], %[j], %[wnl], v125, v[126:127]\n\t"
+      "v_mad_u64_u32 %[x1], %[j], v122, %[nql], %[x1]\n\t"
+      "v_mad_u64_u32 v[126:127], %[j], v122, %[nqh], v[126:127]\n\t"
+      "v_mad_u64_u32 v[126:127], %[j], v123, %[nql], v[126:127]\n\t"
+      "v_lshlrev_b64 v[126:127], 32, v[126:127]\n\t"
+      "v_lshl_add_u64 %[x1], %[x1], 0, v[126:127]"                   // X1 = W N^-1 D mod q in [0, 3q)
+      : [x0] "+v"(x0), [x1] "+v"(x1), [c] "=&s"(c), [j] "=&s"(j), [b] "=&s"(b)
+      : [nil] "s"(lo32(ni)), [nih] "s"(hi32(ni)), [npl] "s"(lo32(nip)), [nph] "s"(hi32(nip)), [wnl] "s"(lo32(wn)),
+        [wnh] "s"(hi32(wn)), [wpl] "s"(lo32(wnp)), [wph] "s"(hi32(wnp)), [q4] "s"(q4), [nql] "s"(lo32(nq)),
+        [nqh] "s"(hi32(nq))
+      : NTTAMD_CLOBBERS);
+}
+
+// x mod q in [0, 3q) for any x < 2^64: a Shoup multiplication by 1 with the
+// companion r = floor(2^64 / q) and the quotient estimate of the wide
+// butterflies.  Brings the forward's wide outputs back into [0, 4q).
+__device__ __forceinline__ u64 reduce_wide(u64 x, u64 r, u64 nq) {
+  u64 c, j, y;
+  asm volatile("v_mad_u64_u32 v[124:125], %[j], %[rl], %[xh], 0\n\t"         // P = lo(r) hi(x) ...
+      "v_mad_u64_u32 v[124:125], %[c], %[rh], %[xl], v[124:125]\n\t" // + hi(r) lo(x), carry c
+      "v_mov_b32 v124, v125\n\t"
+      "s_nop 0\n\t"
+      "v_addc_co_u32 v125, %[j], 0, 0, %[c]\n\t"
+      "v_mad_u64_u32 v[124:125], %[j], %[rh], %[xh], v[124:125]\n\t" // ... Q'
+      "v_mad_u64_u32 v[126:127], %[j], v124, %[nqh], 0\n\t"          // cross products
+      "v_mad_u64_u32 v[126:127], %[j], v125, %[nql], v[126:127]\n\t"
+      "v_mad_u64_u32 v[124:125], %[j], v124, %[nql], %[x]\n\t"       // x + Q'0 nq0
+      "v_lshlrev_b64 v[126:127], 32, v[126:127]\n\t"
+      "v_lshl_add_u64 %[y], v[124:125], 0, v[126:127]"                // x - Q' q in [0, 3q)
+      : [y] "=v"(y), [c] "=&s"(c), [j] "=&s"(j)
+      : [x] "v"(x), [xl] "v"(lo32(x)), [xh] "v"(hi32(x)), [rl] "s"(lo32(r)), [rh] "s"(hi32(r)),
+        [nql] "s"(lo32(nq)), [nqh] "s"(hi32(nq))
+      : "v124", "v125", "v126", "v127");
+  return y;
+}
+
 #undef NTTAMD_CLOBBERS
 
 // Butterfly selection for the transform templates: HAND = the hand-scheduled

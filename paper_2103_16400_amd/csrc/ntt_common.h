@@ -46,6 +46,7 @@ struct PlanView {
   u64 q, q2, nq, nq2;       // nq = 2^64 - q, nq2 = 2^64 - 2q
   u64 ninv, ninv_p, wn, wn_p;
   u64 bk;
+  u64 q3, q4, nq4, rq;      // wide-range constants: 3q, 4q, 2^64 - 4q, floor(2^64 / q)
   u32 qbits;
   const ulonglong2* tw;     // natural table of this direction
   const ulonglong2* twp;    // transposed copy for the single-pass kernel (N <= 2^14)
@@ -64,6 +65,10 @@ __device__ __forceinline__ PlanView load_plan(const u64* plan, bool fwd, u64 N) 
   v.wn_p = h->wn_p;
   v.bk = h->barrett_k;
   v.qbits = (u32)h->qbits;
+  v.q3 = h->q + h->q2;
+  v.q4 = 2 * h->q2;
+  v.nq4 = 0 - v.q4;
+  v.rq = h->barrett_k >> (v.qbits - 1);     // floor(2^(63+Q) / q) / 2^(Q-1) = floor(2^64 / q)
   v.tw = reinterpret_cast<const ulonglong2*>(plan + kPlanHeaderWords) + (fwd ? 0 : N);
   v.twp = v.tw + 2 * N;
   return v;
@@ -108,9 +113,12 @@ __device__ __forceinline__ u64 finish(u64 v, u64 idx, const PassArgs& a, const P
   return (a.flags & kFlagCanon) ? csub(v, pv.q) : v;
 }
 
-ntt_status launch_onchip(const PassArgs& base_args, uint64_t items, bool fwd, hipStream_t stream);
+// wide: use the wide-range butterflies; valid when every modulus of the launch
+// is below kWideModulusBound.
+ntt_status launch_onchip(const PassArgs& base_args, uint64_t items, bool fwd, bool wide, hipStream_t stream);
 // Fused product per limb for N <= 2^14: in = b, mul = NTT(a) lazy, out =
 // canonical product (acc false) or accumulator += product (acc true).
-ntt_status launch_onchip_product(const PassArgs& base_args, uint64_t items, bool acc, hipStream_t stream);
+ntt_status launch_onchip_product(const PassArgs& base_args, uint64_t items, bool acc, bool wide,
+                                 hipStream_t stream);
 
 }  // namespace nttamd

@@ -28,6 +28,8 @@
 // non-temporal.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "internal.h"
 #include "modarith.h"
 #include "ntt_common.h"
@@ -138,6 +140,20 @@ void set_hi_variant(bool fwd, int logN, uint64_t items, int variant) {
 int get_hi_variant(bool fwd, int logN, uint64_t items) { return g_hi_variant[fwd ? 1 : 0][logN][batch_bucket(items)]; }
 int hi_variant_count() { return kVariants; }
 
+static std::atomic<int> g_wide_range{1};
+bool wide_range_enabled() { return g_wide_range.load(std::memory_order_relaxed) != 0; }
+void set_wide_range(bool on) { g_wide_range.store(on ? 1 : 0); }
+
+// The single-pass kernels take the wide-range butterflies when every modulus of
+// the launch is below kWideModulusBound: from inputs below 4q, 14 forward stages
+// keep every value below 46 q < 2^64.
+static bool use_wide(const NttLaunch& l) {
+  if (!wide_range_enabled()) return false;
+  for (uint32_t i = 0; i < l.num_limbs; ++i)
+    if (l.plans[i]->q >= kWideModulusBound) return false;
+  return true;
+}
+
 static ntt_status launch_passes(const NttLaunch& l, bool fwd, int force_variant) {
   const ntt_plan* p0 = l.plans[0];
   const int logN = p0->logN;
@@ -157,7 +173,7 @@ static ntt_status launch_passes(const NttLaunch& l, bool fwd, int force_variant)
     a.out = l.out;
     a.b0 = 0;
     a.flags = last_flags;
-    ntt_status st = launch_onchip(a, items, fwd, l.stream);
+    ntt_status st = launch_onchip(a, items, fwd, use_wide(l), l.stream);
     if (st) return st;
     return hipGetLastError() == hipSuccess ? NTT_OK : NTT_EDEVICE;
   }
@@ -209,7 +225,7 @@ ntt_status launch_product(const NttLaunch& l, bool acc) {
   a.in = l.in;
   a.out = l.out;
   a.mul = l.mul_into;
-  return launch_onchip_product(a, l.num_polys * l.num_limbs, acc, l.stream);
+  return launch_onchip_product(a, l.num_polys * l.num_limbs, acc, use_wide(l), l.stream);
 }
 
 ntt_status launch_forward(const NttLaunch& l) { return launch_passes(l, true, -1); }

@@ -11,8 +11,11 @@
 
 namespace nttamd {
 
-template <bool FWD, int LOGN, int LOGR, bool SPLIT, bool HAND = true>
+// WIDE: the wide-range butterflies (moduli below 2^58); the caller brings the
+// forward's outputs back into [0, 4q) and the inverse's into [0, 2q).
+template <bool FWD, int LOGN, int LOGR, bool SPLIT, bool HAND = true, bool WIDE = false>
 struct OnChip {
+  static_assert(!WIDE || HAND, "the wide-range butterflies exist only hand-scheduled");
   static constexpr int N = 1 << LOGN;
   static constexpr int R = 1 << LOGR;
   static constexpr int NT = N >> LOGR;
@@ -143,9 +146,15 @@ struct OnChip {
           for (int m = 0; m < (1 << p); ++m) {
             const int j = (u << (p + 1)) | m;
             const int j2 = j | (1 << p);
-            if (FWD) bfly_fwd<HAND>(x[j], x[j2], cur[i].x, cur[i].y, pv.q2, pv.nq, pv.nq2);
-            else if (fused_last) bfly_inv_last<HAND>(x[j], x[j2], pv.ninv, pv.ninv_p, pv.wn, pv.wn_p, pv.q2, pv.nq);
-            else bfly_inv<HAND>(x[j], x[j2], cur[i].x, cur[i].y, pv.q2, pv.nq, pv.nq2);
+            if constexpr (WIDE) {
+              if (FWD) harvey_fwd_wide(x[j], x[j2], cur[i].x, cur[i].y, pv.q3, pv.nq);
+              else if (fused_last) harvey_inv_last_wide(x[j], x[j2], pv.ninv, pv.ninv_p, pv.wn, pv.wn_p, pv.q4, pv.nq);
+              else harvey_inv_wide(x[j], x[j2], cur[i].x, cur[i].y, pv.q4, pv.nq, pv.nq4);
+            } else {
+              if (FWD) bfly_fwd<HAND>(x[j], x[j2], cur[i].x, cur[i].y, pv.q2, pv.nq, pv.nq2);
+              else if (fused_last) bfly_inv_last<HAND>(x[j], x[j2], pv.ninv, pv.ninv_p, pv.wn, pv.wn_p, pv.q2, pv.nq);
+              else bfly_inv<HAND>(x[j], x[j2], cur[i].x, cur[i].y, pv.q2, pv.nq, pv.nq2);
+            }
           }
         }
         stage_fence();
@@ -172,12 +181,22 @@ __device__ __forceinline__ u32 opaque(u32 v) {
   return v;
 }
 
+// Brings a wide-range transform output into the ranges of the paper's
+// butterflies: the forward's [0, 4q) (here [0, 3q)), the inverse's [0, 2q).
+template <bool FWD, bool WIDE>
+__device__ __forceinline__ u64 unwiden(u64 v, const PlanView& pv) {
+  if constexpr (!WIDE) return v;
+  else if constexpr (FWD) return reduce_wide(v, pv.rq, pv.nq);
+  else return csub(v, pv.q2);
+}
+
 // Transforms one limb: reads `in` (N coefficients), writes `out`; the output
 // step applies MODE with the per-item multiplier / accumulator `mul`.
-template <bool FWD, int LOGN, int LOGR, bool SPLIT, int MODE, bool HAND = true>
+template <bool FWD, int LOGN, int LOGR, bool SPLIT, int MODE, bool HAND = true, bool WIDE = false>
 __device__ __forceinline__ void onchip_body(const PlanView& pv, const u64* in, u64* out, const u64* mul,
-                                            typename OnChip<FWD, LOGN, LOGR, SPLIT, HAND>::W* lds, bool nt_load) {
-  using K = OnChip<FWD, LOGN, LOGR, SPLIT, HAND>;
+                                            typename OnChip<FWD, LOGN, LOGR, SPLIT, HAND, WIDE>::W* lds,
+                                            bool nt_load) {
+  using K = OnChip<FWD, LOGN, LOGR, SPLIT, HAND, WIDE>;
   constexpr int R = K::R;
   constexpr int NT = K::NT;
   constexpr int RL = K::G::NR - 1;
@@ -202,6 +221,12 @@ __device__ __forceinline__ void onchip_body(const PlanView& pv, const u64* in, u
   }
 
   K::template run<0>(lds, x, t, pv);
+  if constexpr (WIDE && FWD) {
+    // before the output loop, so that its loads (fused multiply) can be grouped:
+    // the compiler does not move memory accesses across these statements
+#pragma unroll
+    for (int j = 0; j < R; ++j) x[j] = unwiden<true, true>(x[j], pv);
+  }
 
   if constexpr (!direct_out) {
     const u32 bo = K::template row_base<RL>(t);
@@ -210,7 +235,7 @@ __device__ __forceinline__ void onchip_body(const PlanView& pv, const u64* in, u
 #pragma unroll
   for (int j = 0; j < R; ++j) {
     const u32 i = direct_out ? K::template rho<RL>(t, j) : (u32)j * NT + t;
-    out[i] = finish_item<FWD, MODE>(x[j], mul, i, pv);
+    out[i] = finish_item<FWD, MODE>(FWD ? x[j] : unwiden<false, WIDE>(x[j], pv), mul, i, pv);
     if ((j & 7) == 7) stage_fence();
   }
 }
@@ -223,13 +248,13 @@ __device__ __forceinline__ void onchip_body(const PlanView& pv, const u64* in, u
 // the coefficients t R .. t R + R - 1, so the product and the inverse start
 // in registers.  Every thread reads its multipliers before the inverse's
 // first LDS barrier, so out may equal m.
-template <int LOGN, int LOGR, bool SPLIT, int MODE, bool HAND = true>
+template <int LOGN, int LOGR, bool SPLIT, int MODE, bool HAND = true, bool WIDE = false>
 __device__ __forceinline__ void onchip_product_body(const PlanView& pf, const PlanView& pi, const u64* b,
                                                     const u64* m, u64* out,
-                                                    typename OnChip<true, LOGN, LOGR, SPLIT, HAND>::W* lds,
+                                                    typename OnChip<true, LOGN, LOGR, SPLIT, HAND, WIDE>::W* lds,
                                                     bool nt_load) {
-  using KF = OnChip<true, LOGN, LOGR, SPLIT, HAND>;
-  using KI = OnChip<false, LOGN, LOGR, SPLIT, HAND>;
+  using KF = OnChip<true, LOGN, LOGR, SPLIT, HAND, WIDE>;
+  using KI = OnChip<false, LOGN, LOGR, SPLIT, HAND, WIDE>;
   constexpr int R = KF::R;
   constexpr int NT = KF::NT;
   constexpr int RLF = KF::G::NR - 1;
@@ -255,6 +280,12 @@ __device__ __forceinline__ void onchip_product_body(const PlanView& pf, const Pl
     KF::shuffle(lds, x, [&](int j) { return KF::lin_row(t, j); }, [&](int j) { return bi + KF::template row_off<0>(j); });
   }
   KF::template run<0>(lds, x, t, pf);
+  if constexpr (WIDE) {
+    // all reductions first: the compiler does not move the multiplier loads across
+    // these statements, and grouped loads hide their latency
+#pragma unroll
+    for (int j = 0; j < R; ++j) x[j] = unwiden<true, true>(x[j], pf);
+  }
   const u64* mt = m + ((u64)opaque(t) << LOGR);  // KF::rho<RLF>(t, j) = t R + j
 #pragma unroll
   for (int j = 0; j < R; ++j) {
@@ -271,7 +302,7 @@ __device__ __forceinline__ void onchip_product_body(const PlanView& pf, const Pl
 #pragma unroll
   for (int j = 0; j < R; ++j) {
     const u32 i = direct_out ? KI::template rho<RLI>(to, j) : (u32)j * NT + to;
-    out[i] = finish_item<false, MODE>(x[j], out, i, pi);
+    out[i] = finish_item<false, MODE>(unwiden<false, WIDE>(x[j], pi), out, i, pi);
     if ((j & 7) == 7) stage_fence();
   }
 }

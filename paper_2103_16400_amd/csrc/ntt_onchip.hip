@@ -30,90 +30,96 @@
 namespace nttamd {
 
 // MINW: waves per SIMD the register allocation must allow (occupancy target).
-template <bool FWD, int LOGN, int LOGR, bool SPLIT, int MINW, int MODE>
+template <bool FWD, int LOGN, int LOGR, bool SPLIT, int MINW, int MODE, bool WIDE>
 __global__ void __launch_bounds__(1 << (LOGN - LOGR), MINW) ntt_onchip_kernel(const PassArgs a) {
   static_assert(MINW <= 4, "the butterflies use v122..v127: keep a budget of at least 128 VGPRs");
-  using K = OnChip<FWD, LOGN, LOGR, SPLIT>;
+  using K = OnChip<FWD, LOGN, LOGR, SPLIT, true, WIDE>;
   __shared__ typename K::W lds[K::LDSW];
   const u32 item = a.item0 + blockIdx.x;
   const PlanView pv = load_plan(a.plan[item % a.num_limbs], FWD, (u64)K::N);
   const u64 base = (u64)item << LOGN;
-  onchip_body<FWD, LOGN, LOGR, SPLIT, MODE>(pv, a.in + base, a.out + base, a.mul ? a.mul + base : nullptr, lds, true);
+  onchip_body<FWD, LOGN, LOGR, SPLIT, MODE, true, WIDE>(pv, a.in + base, a.out + base, a.mul ? a.mul + base : nullptr, lds, true);
 }
 
 // Fused negacyclic product per limb: in = b, mul = NTT(a) (lazy), out =
 // result (MODE canonical) or accumulator (MODE accumulate; may equal mul).
-template <int LOGN, int LOGR, bool SPLIT, int MINW, int MODE>
+template <int LOGN, int LOGR, bool SPLIT, int MINW, int MODE, bool WIDE>
 __global__ void __launch_bounds__(1 << (LOGN - LOGR), MINW) ntt_onchip_product_kernel(const PassArgs a) {
   static_assert(MINW <= 4, "the butterflies use v122..v127: keep a budget of at least 128 VGPRs");
-  using K = OnChip<true, LOGN, LOGR, SPLIT>;
+  using K = OnChip<true, LOGN, LOGR, SPLIT, true, WIDE>;
   __shared__ typename K::W lds[K::LDSW];
   const u32 item = a.item0 + blockIdx.x;
   const u64* plan = a.plan[item % a.num_limbs];
   const PlanView pf = load_plan(plan, true, (u64)K::N);
   const PlanView pi = load_plan(plan, false, (u64)K::N);
   const u64 base = (u64)item << LOGN;
-  onchip_product_body<LOGN, LOGR, SPLIT, MODE>(pf, pi, a.in + base, a.mul + base, a.out + base, lds, true);
+  onchip_product_body<LOGN, LOGR, SPLIT, MODE, true, WIDE>(pf, pi, a.in + base, a.mul + base, a.out + base, lds, true);
 }
 
 typedef void (*OnchipKernel)(const PassArgs);
 
-template <bool FWD, int MODE>
+template <bool FWD, int MODE, bool WIDE>
 static OnchipKernel pick_onchip_mode(int logN) {
   switch (logN) {
-    case 1: return ntt_onchip_kernel<FWD, 1, onchip_logr(1), false, 1, MODE>;
-    case 2: return ntt_onchip_kernel<FWD, 2, onchip_logr(2), false, 1, MODE>;
-    case 3: return ntt_onchip_kernel<FWD, 3, onchip_logr(3), false, 1, MODE>;
-    case 4: return ntt_onchip_kernel<FWD, 4, onchip_logr(4), false, 1, MODE>;
-    case 5: return ntt_onchip_kernel<FWD, 5, onchip_logr(5), false, 1, MODE>;
-    case 6: return ntt_onchip_kernel<FWD, 6, onchip_logr(6), false, 1, MODE>;
-    case 7: return ntt_onchip_kernel<FWD, 7, onchip_logr(7), false, 1, MODE>;
-    case 8: return ntt_onchip_kernel<FWD, 8, onchip_logr(8), false, 1, MODE>;
-    case 9: return ntt_onchip_kernel<FWD, 9, onchip_logr(9), false, 2, MODE>;
-    case 10: return ntt_onchip_kernel<FWD, 10, onchip_logr(10), false, 2, MODE>;
-    case 11: return ntt_onchip_kernel<FWD, 11, onchip_logr(11), false, 2, MODE>;
-    case 12: return ntt_onchip_kernel<FWD, 12, onchip_logr(12), false, 4, MODE>;
-    case 13: return ntt_onchip_kernel<FWD, 13, onchip_logr(13), true, 4, MODE>;
-    case 14: return ntt_onchip_kernel<FWD, 14, onchip_logr(14), true, 4, MODE>;
+    case 1: return ntt_onchip_kernel<FWD, 1, onchip_logr(1), false, 1, MODE, WIDE>;
+    case 2: return ntt_onchip_kernel<FWD, 2, onchip_logr(2), false, 1, MODE, WIDE>;
+    case 3: return ntt_onchip_kernel<FWD, 3, onchip_logr(3), false, 1, MODE, WIDE>;
+    case 4: return ntt_onchip_kernel<FWD, 4, onchip_logr(4), false, 1, MODE, WIDE>;
+    case 5: return ntt_onchip_kernel<FWD, 5, onchip_logr(5), false, 1, MODE, WIDE>;
+    case 6: return ntt_onchip_kernel<FWD, 6, onchip_logr(6), false, 1, MODE, WIDE>;
+    case 7: return ntt_onchip_kernel<FWD, 7, onchip_logr(7), false, 1, MODE, WIDE>;
+    case 8: return ntt_onchip_kernel<FWD, 8, onchip_logr(8), false, 1, MODE, WIDE>;
+    case 9: return ntt_onchip_kernel<FWD, 9, onchip_logr(9), false, 2, MODE, WIDE>;
+    case 10: return ntt_onchip_kernel<FWD, 10, onchip_logr(10), false, 2, MODE, WIDE>;
+    case 11: return ntt_onchip_kernel<FWD, 11, onchip_logr(11), false, 2, MODE, WIDE>;
+    case 12: return ntt_onchip_kernel<FWD, 12, onchip_logr(12), false, 4, MODE, WIDE>;
+    case 13: return ntt_onchip_kernel<FWD, 13, onchip_logr(13), true, 4, MODE, WIDE>;
+    case 14: return ntt_onchip_kernel<FWD, 14, onchip_logr(14), true, 4, MODE, WIDE>;
     default: return nullptr;
   }
 }
 
-static OnchipKernel pick_onchip(bool fwd, int logN, u32 flags) {
+template <bool WIDE>
+static OnchipKernel pick_onchip_w(bool fwd, int logN, u32 flags) {
   if (fwd) {
-    if (flags & kFlagMul) return pick_onchip_mode<true, kOutMul>(logN);
-    if (flags & kFlagCanon) return pick_onchip_mode<true, kOutCanon>(logN);
-    return pick_onchip_mode<true, kOutLazy>(logN);
+    if (flags & kFlagMul) return pick_onchip_mode<true, kOutMul, WIDE>(logN);
+    if (flags & kFlagCanon) return pick_onchip_mode<true, kOutCanon, WIDE>(logN);
+    return pick_onchip_mode<true, kOutLazy, WIDE>(logN);
   }
-  if (flags & kFlagAcc) return pick_onchip_mode<false, kOutAcc>(logN);
-  if (flags & kFlagCanon) return pick_onchip_mode<false, kOutCanon>(logN);
-  return pick_onchip_mode<false, kOutLazy>(logN);
+  if (flags & kFlagAcc) return pick_onchip_mode<false, kOutAcc, WIDE>(logN);
+  if (flags & kFlagCanon) return pick_onchip_mode<false, kOutCanon, WIDE>(logN);
+  return pick_onchip_mode<false, kOutLazy, WIDE>(logN);
 }
 
-template <int MODE>
+static OnchipKernel pick_onchip(bool fwd, int logN, u32 flags, bool wide) {
+  return wide ? pick_onchip_w<true>(fwd, logN, flags) : pick_onchip_w<false>(fwd, logN, flags);
+}
+
+template <int MODE, bool WIDE>
 static OnchipKernel pick_product(int logN) {
   switch (logN) {
-    case 1: return ntt_onchip_product_kernel<1, onchip_logr(1), false, 1, MODE>;
-    case 2: return ntt_onchip_product_kernel<2, onchip_logr(2), false, 1, MODE>;
-    case 3: return ntt_onchip_product_kernel<3, onchip_logr(3), false, 1, MODE>;
-    case 4: return ntt_onchip_product_kernel<4, onchip_logr(4), false, 1, MODE>;
-    case 5: return ntt_onchip_product_kernel<5, onchip_logr(5), false, 1, MODE>;
-    case 6: return ntt_onchip_product_kernel<6, onchip_logr(6), false, 1, MODE>;
-    case 7: return ntt_onchip_product_kernel<7, onchip_logr(7), false, 1, MODE>;
-    case 8: return ntt_onchip_product_kernel<8, onchip_logr(8), false, 1, MODE>;
-    case 9: return ntt_onchip_product_kernel<9, onchip_logr(9), false, 2, MODE>;
-    case 10: return ntt_onchip_product_kernel<10, onchip_logr(10), false, 2, MODE>;
-    case 11: return ntt_onchip_product_kernel<11, onchip_logr(11), false, 2, MODE>;
-    case 12: return ntt_onchip_product_kernel<12, onchip_logr(12), false, 4, MODE>;
-    case 13: return ntt_onchip_product_kernel<13, onchip_logr(13), true, 4, MODE>;
-    case 14: return ntt_onchip_product_kernel<14, onchip_logr(14), true, 4, MODE>;
+    case 1: return ntt_onchip_product_kernel<1, onchip_logr(1), false, 1, MODE, WIDE>;
+    case 2: return ntt_onchip_product_kernel<2, onchip_logr(2), false, 1, MODE, WIDE>;
+    case 3: return ntt_onchip_product_kernel<3, onchip_logr(3), false, 1, MODE, WIDE>;
+    case 4: return ntt_onchip_product_kernel<4, onchip_logr(4), false, 1, MODE, WIDE>;
+    case 5: return ntt_onchip_product_kernel<5, onchip_logr(5), false, 1, MODE, WIDE>;
+    case 6: return ntt_onchip_product_kernel<6, onchip_logr(6), false, 1, MODE, WIDE>;
+    case 7: return ntt_onchip_product_kernel<7, onchip_logr(7), false, 1, MODE, WIDE>;
+    case 8: return ntt_onchip_product_kernel<8, onchip_logr(8), false, 1, MODE, WIDE>;
+    case 9: return ntt_onchip_product_kernel<9, onchip_logr(9), false, 2, MODE, WIDE>;
+    case 10: return ntt_onchip_product_kernel<10, onchip_logr(10), false, 2, MODE, WIDE>;
+    case 11: return ntt_onchip_product_kernel<11, onchip_logr(11), false, 2, MODE, WIDE>;
+    case 12: return ntt_onchip_product_kernel<12, onchip_logr(12), false, 4, MODE, WIDE>;
+    case 13: return ntt_onchip_product_kernel<13, onchip_logr(13), true, 4, MODE, WIDE>;
+    case 14: return ntt_onchip_product_kernel<14, onchip_logr(14), true, 4, MODE, WIDE>;
     default: return nullptr;
   }
 }
 
-ntt_status launch_onchip_product(const PassArgs& base_args, uint64_t items, bool acc, hipStream_t stream) {
+ntt_status launch_onchip_product(const PassArgs& base_args, uint64_t items, bool acc, bool wide, hipStream_t stream) {
   const int logN = (int)base_args.logN;
-  OnchipKernel k = acc ? pick_product<kOutAcc>(logN) : pick_product<kOutCanon>(logN);
+  OnchipKernel k = wide ? (acc ? pick_product<kOutAcc, true>(logN) : pick_product<kOutCanon, true>(logN))
+                        : (acc ? pick_product<kOutAcc, false>(logN) : pick_product<kOutCanon, false>(logN));
   if (!k) return NTT_EINVAL_DEGREE;
   PassArgs a = base_args;
   const uint64_t kMaxX = 1u << 30;
@@ -125,9 +131,9 @@ ntt_status launch_onchip_product(const PassArgs& base_args, uint64_t items, bool
   return hipGetLastError() == hipSuccess ? NTT_OK : NTT_EDEVICE;
 }
 
-ntt_status launch_onchip(const PassArgs& base_args, uint64_t items, bool fwd, hipStream_t stream) {
+ntt_status launch_onchip(const PassArgs& base_args, uint64_t items, bool fwd, bool wide, hipStream_t stream) {
   const int logN = (int)base_args.logN;
-  OnchipKernel k = pick_onchip(fwd, logN, base_args.flags);
+  OnchipKernel k = pick_onchip(fwd, logN, base_args.flags, wide);
   if (!k) return NTT_EINVAL_DEGREE;
   PassArgs a = base_args;
   const uint64_t kMaxX = 1u << 30;

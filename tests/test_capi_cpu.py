@@ -158,3 +158,16 @@ def test_validation_toggle_without_device(nt):
     finally:
         L.ntt_set_validate(was)
     assert nt.NTT_ERANGE == -13 and "outside" in nt.status_string(nt.NTT_ERANGE)
+
+
+def test_wide_range_switch_without_device(nt):
+    """The wide-range butterflies are on by default and switch off and on again."""
+    L = _raw(nt)
+    assert L.ntt_get_wide_range() == 1 and nt.get_wide_range()
+    try:
+        assert L.ntt_set_wide_range(0) == nt.NTT_OK and L.ntt_get_wide_range() == 0
+        assert not nt.get_wide_range()
+        nt.set_wide_range(True)
+        assert L.ntt_get_wide_range() == 1
+    finally:
+        L.ntt_set_wide_range(1)
