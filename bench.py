@@ -42,11 +42,11 @@ HBM_PEAK_GBS = 8000.0
 #   valu_insts             SQ_INSTS_VALU (wave-level VALU instructions per dispatch).
 # Valid only for the kernel sources they were taken with, identified by the SHA-256 of these files.
 COUNTERS_N16384 = {
-    "sources": ["ntt_onchip.hip", "ntt_onchip.h", "ntt_common.h", "modarith.h", "internal.h"],
-    "sha256": "502f0621b02dcd193aca81ace3de7928f4bd31fb37489090ca9a78dee94adbc0",
+    "sources": ["ntt_onchip.hip", "ntt_onchip.h", "ntt_common.h", "modarith.h", "internal.h", "ntt_kernels.hip"],
+    "sha256": "ab68c9788f3f933a213f9bbdd15ada8c2d8f030872da4ed72023b522318f5b6b",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "product": {"fetch_kib": 832664.5, "write_kib": 540672.0, "valu_insts": 427556864},
-    "forward": {"fetch_kib": 275435.0, "write_kib": 524288.2, "valu_insts": 175996928},
+    "product": {"fetch_kib": 837197.9792, "write_kib": 573440.0, "valu_insts": 372539392},
+    "forward": {"fetch_kib": 278550.6875, "write_kib": 524288.0, "valu_insts": 141918208},
 }
 
 # VALU issue capacity: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at 2.4 GHz

@@ -420,7 +420,7 @@ __device__ __forceinline__ u64 reduce4(u64 x, u64 q, u64 q2) { return csub(csub(
 //   c1 = (x y) >> (Q - 1);  c3 = floor(c1 k / 2^64);  c4 = x y - c3 q.
 // The quotient estimate c3 can be short by up to 2, so c4 < 3q and two
 // conditional subtractions give the canonical value.
-template <int F>
+template <int F, bool CANON = true>
 __device__ __forceinline__ u64 barrett_mulmod(u64 x, u64 y, u64 q, u64 q2, u64 k, u32 qbits) {
   if (F >= 4) { x = csub(x, q2); y = csub(y, q2); }
   if (F >= 2) { x = csub(x, q); y = csub(y, q); }
@@ -430,6 +430,7 @@ __device__ __forceinline__ u64 barrett_mulmod(u64 x, u64 y, u64 q, u64 q2, u64 k
   const u64 c1 = (lo >> s) | (hi << (64 - s));
   const u64 c3 = mulhi64(c1, k);
   u64 c4 = lo - c3 * q;
+  if constexpr (!CANON) return c4;                   // [0, 3q): for consumers that accept it
   c4 = csub(c4, q);
   return csub(c4, q);
 }

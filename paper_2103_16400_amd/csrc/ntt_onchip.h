@@ -247,7 +247,9 @@ __device__ __forceinline__ void onchip_body(const PlanView& pv, const u64* in, u
 // the forward's last round and the inverse's first round both give thread t
 // the coefficients t R .. t R + R - 1, so the product and the inverse start
 // in registers.  Every thread reads its multipliers before the inverse's
-// first LDS barrier, so out may equal m.
+// first LDS barrier, so out may equal m.  With WIDE, the forward's outputs are
+// first brought into [0, 3q), and the multiply leaves its remainder in [0, 3q)
+// (no final corrections), which the wide inverse accepts.
 template <int LOGN, int LOGR, bool SPLIT, int MODE, bool HAND = true, bool WIDE = false>
 __device__ __forceinline__ void onchip_product_body(const PlanView& pf, const PlanView& pi, const u64* b,
                                                     const u64* m, u64* out,
@@ -289,7 +291,8 @@ __device__ __forceinline__ void onchip_product_body(const PlanView& pf, const Pl
   const u64* mt = m + ((u64)opaque(t) << LOGR);  // KF::rho<RLF>(t, j) = t R + j
 #pragma unroll
   for (int j = 0; j < R; ++j) {
-    x[j] = barrett_mulmod<4>(x[j], mt[j], pf.q, pf.q2, pf.bk, pf.qbits);
+    // the wide inverse takes inputs in [0, 4q): Algorithm 8's remainder in [0, 3q) suffices
+    x[j] = barrett_mulmod<4, !WIDE>(x[j], mt[j], pf.q, pf.q2, pf.bk, pf.qbits);
     if ((j & 7) == 7) stage_fence();
   }
   __syncthreads();                                // the forward's last LDS reads precede the inverse's writes
