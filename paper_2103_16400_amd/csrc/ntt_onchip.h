@@ -22,9 +22,13 @@ struct OnChip {
   static constexpr int LDSW = N + (N >> LOGR);
   // transposed sub-tables are laid out for onchip_logr(LOGN) coefficients per thread
   static constexpr int PERM_TOP = LOGR == onchip_logr(LOGN) ? onchip_perm_top(FWD, LOGN) : -1;
-  // twiddle pairs per prefetch block (one for the hand-scheduled forward at 32
-  // coefficients per thread, which needs the registers to stay within 128)
-  static constexpr int TB = HAND && FWD && LOGR >= 5 ? 1 : 2;
+  // Twiddle pairs per prefetch block.  The next block's loads are issued before
+  // the current block's butterflies, so in the short-stride stages (one
+  // butterfly per twiddle) a block must hold enough butterflies to cover the
+  // latency of an L2 hit.  At 32 coefficients per thread the 128-register
+  // budget allows one pair with the paper's forward butterflies and three with
+  // the wide ones (measured fastest; four spill).
+  static constexpr int TB = HAND && FWD && LOGR >= 5 ? (WIDE ? 3 : 1) : 2;
   using G = Geo<FWD, LOGN, LOGR>;
   using W = typename std::conditional<SPLIT, u32, u64>::type;
 
