@@ -43,10 +43,10 @@ HBM_PEAK_GBS = 8000.0
 # Valid only for the kernel sources they were taken with, identified by the SHA-256 of these files.
 COUNTERS_N16384 = {
     "sources": ["ntt_onchip.hip", "ntt_onchip.h", "ntt_common.h", "modarith.h", "internal.h", "ntt_kernels.hip"],
-    "sha256": "ab68c9788f3f933a213f9bbdd15ada8c2d8f030872da4ed72023b522318f5b6b",
+    "sha256": "516e57be2cb3d3d1fade9a547bbbfb4ef395812fcf63b69caeda2e7f4f35dd27",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "product": {"fetch_kib": 837197.9792, "write_kib": 573440.0, "valu_insts": 372539392},
-    "forward": {"fetch_kib": 278550.6875, "write_kib": 524288.0, "valu_insts": 141918208},
+    "product": {"fetch_kib": 863582.5417, "write_kib": 589824.0, "valu_insts": 382697472},
+    "forward": {"fetch_kib": 277789.9583, "write_kib": 524288.2083, "valu_insts": 141918208},
 }
 
 # VALU issue capacity: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at 2.4 GHz
