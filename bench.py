@@ -18,6 +18,9 @@ Also reported, on the same JSON line:
                 average duration (HIP events on the launch stream) against 8 TB/s,
                 with the VALU issue share beside it; roofline_fwd gives the same
                 for the forward transform of the other operand;
+  roofline_alu  the same two kernels against the VALU's peak (the bound that
+                binds them): measured VALU lane instructions per second over
+                256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz;
   cpu_baseline  the CPU oracle (O(N^2) direct forward transform) on a bounded
                 sample, timed on this host's cores.
 """
@@ -51,6 +54,8 @@ COUNTERS_N16384 = {
 
 # VALU issue capacity: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at 2.4 GHz
 VALU_WAVE_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
+# the same capacity in 32-bit lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (39.3 T/s)
+VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 
 
 def counters_valid(c):
@@ -69,6 +74,19 @@ def measured_traffic(c, kernel):
     if not counters_valid(c) or k["fetch_kib"] is None:
         return None
     return int((k["fetch_kib"] * c["fetch_scale"] + k["write_kib"] * c["write_scale"]) * 1024)
+
+
+def alu_roofline(c, kernel, avg_ms, desc):
+    """The kernel against the VALU's peak: its measured VALU lane instructions (SQ_INSTS_VALU x 64)
+    per second over 39.3 T lane-ops/s; None once the kernel sources changed."""
+    k = c[kernel]
+    if not counters_valid(c) or k["valu_insts"] is None:
+        return None
+    a = k["valu_insts"] * 64 / (avg_ms * 1e-3)
+    return {"bound": "alu", "achieved": round(a / 1e12, 3), "peak": round(VALU_LANE_OPS_PER_S / 1e12, 3),
+            "unit": "T lane-op/s", "frac": round(a / VALU_LANE_OPS_PER_S, 4), "kernel": desc,
+            "avg_ms": round(avg_ms, 4), "valu_lane_ops": k["valu_insts"] * 64,
+            "source": "SQ_INSTS_VALU per launch (rocprofv3 --pmc) x 64 lanes"}
 
 
 def valu_share(c, kernel, avg_ms):
@@ -538,6 +556,11 @@ def main():
                          "inverse, accumulate; %d limbs, one launch" % limbs, prod_bytes, prod_ms),
         "roofline_fwd": roof("forward", "ntt_onchip_kernel<fwd, N=2^14>: forward NTT of %d limbs, one launch"
                              % limbs, fwd_bytes, fwd_ms),
+        "roofline_alu": alu_roofline(COUNTERS_N16384, "product", prod_ms,
+                                     "ntt_onchip_product_kernel<N=2^14> (the binding bound of the dominant kernel)")
+        if counted else None,
+        "roofline_alu_fwd": alu_roofline(COUNTERS_N16384, "forward", fwd_ms, "ntt_onchip_kernel<fwd, N=2^14>")
+        if counted else None,
         "step_kernels_ms": {"fwd_lazy": round(fwd_ms, 4), "fwd_mul_inv_acc_fused": round(prod_ms, 4)},
         "p10_p50_p90_ms": {"step_events": pct(step_all), "fwd_lazy": pct(fwd_all),
                            "fwd_mul_inv_acc_fused": pct(prod_all)},
