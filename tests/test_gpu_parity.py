@@ -733,3 +733,43 @@ def test_batch_rejects_bad_items(nt):
         batch.run([(nt.BATCH_FWD, d, d, None, None, 1024, q)] * 5)
     assert e.value.status == nt.NTT_EINVAL_COUNT
     batch.close()
+
+
+def test_bench_step_full_size(nt):
+    """The benchmark's step at its full size and launch configuration: 512 polynomials x 8
+    limbs of the 50-bit primes at N = 2^14, forward(a) 1 -> 4 in one launch, then the fused
+    on-chip product accumulating into acc in one launch.  Checked three ways: sampled outputs
+    against the oracle's negacyclic product (Section 2), the whole arrays against the same
+    step run with the paper's butterflies (ntt_set_wide_range(0)), and every forward output
+    inside [0, 4q)."""
+    import torch
+    N = PRIMES["rns_16384"]["N"]
+    moduli = PRIMES["rns_16384"]["moduli"]
+    L, B = len(moduli), 512
+    a = _rns_inputs(950, N, moduli, B, 1)
+    b = _rns_inputs(951, N, moduli, B, 1)
+    acc0 = _rns_inputs(952, N, moduli, B, 1)
+    da, db = to_dev(a), to_dev(b)
+    results = {}
+    try:
+        for wide in (True, False):
+            nt.set_wide_range(wide)
+            a_ntt = empty_dev(a.size)
+            nt.ntt_forward_rns(a_ntt, da, N, moduli, B, 1, 4)
+            acc = to_dev(acc0)
+            nt.poly_mul_acc_ntt_rns(acc, a_ntt, db, N, moduli, B)
+            torch.cuda.synchronize()
+            qs = torch.tensor([4 * q for q in moduli], dtype=torch.int64, device="cuda:0").repeat(B)
+            assert bool((a_ntt.view(B * L, N) < qs[:, None]).all()), wide
+            results[wide] = acc
+            del a_ntt
+    finally:
+        nt.set_wide_range(True)
+    assert torch.equal(results[True], results[False])
+    got = from_dev(results[True])
+    idx = _sample_idx(N, 953, 6)
+    for p, l in [(0, 0), (1, 7), (255, 3), (511, 5), (511, 7)]:
+        q = moduli[l]
+        s = slice((p * L + l) * N, (p * L + l + 1) * N)
+        want = oracle.eltwise_add(acc0[s][idx], oracle.negacyclic_mul_at(a[s], b[s], idx, q), q)
+        assert np.array_equal(got[s][idx], want), (p, l)
