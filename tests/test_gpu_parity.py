@@ -773,3 +773,64 @@ def test_bench_step_full_size(nt):
         s = slice((p * L + l) * N, (p * L + l + 1) * N)
         want = oracle.eltwise_add(acc0[s][idx], oracle.negacyclic_mul_at(a[s], b[s], idx, q), q)
         assert np.array_equal(got[s][idx], want), (p, l)
+
+
+def test_batch_full_size_uneven(nt):
+    """The benchmark's uneven batch at its full size and launch configuration: 256
+    polynomials, N uniform in {2^12..2^15}, 2..16 limbs of the 50-bit pool (2371 limb
+    transforms), the grid autotuned, run as one persistent launch and from a captured
+    graph.  Every limb's forward (1 -> 4) and inverse (1 -> 1) equals the per-call path's
+    words on the whole array (the paper's butterflies on both sides), and sampled limbs
+    equal the oracle's transforms at sampled indices."""
+    import torch
+    from synthetic import uniform_int
+    pool = PRIMES["uneven"]["moduli"]
+    P = 256
+    logNs = uniform_int(unit_seed(4, 0), P, 12, 15)
+    Ls = uniform_int(unit_seed(4, 1), P, 2, 16)
+    limbs = [(int(logNs[p]), pool[l]) for p in range(P) for l in range(int(Ls[p]))]
+    total = sum(1 << n for n, _ in limbs)
+    host = np.empty(total, dtype=np.uint64)
+    offs, off = [], 0
+    for k, (n, q) in enumerate(limbs):
+        N = 1 << n
+        host[off:off + N] = uniform_mod(unit_seed(5, k, q), N, q)
+        offs.append(off)
+        off += N
+    src = to_dev(host)
+    dst, ref = empty_dev(total), empty_dev(total)
+    batch = nt.Batch(len(limbs))
+    samples = [0, 1, len(limbs) // 2, len(limbs) - 1]
+    try:
+        nt.set_wide_range(False)      # the batch kernel runs the paper's butterflies; so does the reference
+        for op, fwd in ((nt.BATCH_FWD_LAZY, True), (nt.BATCH_INV, False)):
+            items, cnt = nt.Batch.make_items([(op, dst[o:o + (1 << n)], src[o:o + (1 << n)], None, None, 1 << n, q)
+                                              for o, (n, q) in zip(offs, limbs)])
+            batch.autotune(items, cnt)
+            for graph in (False, True):
+                dst.zero_()
+                batch.run(items, cnt, graph=graph)
+                for o, (n, q) in zip(offs, limbs):
+                    N = 1 << n
+                    if fwd:
+                        nt.ntt_forward(ref[o:o + N], src[o:o + N], N, q, 1, 4)
+                    else:
+                        nt.ntt_inverse(ref[o:o + N], src[o:o + N], N, q, 1, 1)
+                torch.cuda.synchronize()
+                assert torch.equal(dst, ref), (op, graph)
+            got = from_dev(dst)
+            for k in samples:
+                n, q = limbs[k]
+                N, o = 1 << n, offs[k]
+                a = host[o:o + N]
+                idx = _sample_idx(N, 960 + k, 8)
+                psi = oracle.min_root(N, q)
+                want = oracle.ntt_forward_at(a, idx, q, psi) if fwd else oracle.ntt_inverse_at(a, idx, q, psi)
+                assert np.array_equal(got[o:o + N][idx] % np.uint64(q), want), (op, k)
+                if fwd:
+                    assert np.all(got[o:o + N] < np.uint64(4 * q))
+                else:
+                    assert np.all(got[o:o + N] < np.uint64(q))
+    finally:
+        nt.set_wide_range(True)
+        batch.close()
