@@ -206,3 +206,35 @@ def test_product32_pipeline_matches_64bit_path(nt):
     r64 = empty_dev(a.size)
     nt.poly_mul_rns(r64, to_dev(a), to_dev(b), N, moduli, B, None)
     assert np.array_equal(host32(r32), from_dev(r64))
+
+
+def test_small_prime_step_full_size(nt):
+    """The benchmark's word-size-2^32 step at its full size: 512 polynomials x 8 limbs of the
+    largest primes below 2^30 at N = 2^14, forward(a) 1 -> 4 then the fused product into acc,
+    twice (so acc accumulates).  The canonical accumulator equals the 64-bit path's on the same
+    moduli word for word over the whole array, and sampled outputs equal the oracle's
+    negacyclic products (Section 2)."""
+    import torch
+    from gpu_util import empty_dev, from_dev, to_dev
+    N = PRIMES["small_16384"]["N"]
+    moduli = SMALL
+    L, B = len(moduli), 512
+    a = _inputs(260, N, moduli, B, 1)
+    b = _inputs(261, N, moduli, B, 1)
+    da32, db32 = dev32(a), dev32(b)
+    c32, acc32 = empty32(a.size), torch.zeros(a.size, dtype=torch.int32, device="cuda:0")
+    da64, db64 = to_dev(a), to_dev(b)
+    c64, acc64 = empty_dev(a.size), torch.zeros(a.size, dtype=torch.int64, device="cuda:0")
+    for _ in range(2):
+        nt.ntt_forward_rns32(c32, da32, N, moduli, B, 1, 4)
+        nt.poly_mul_acc_ntt_rns32(acc32, c32, db32, N, moduli, B)
+        nt.ntt_forward_rns(c64, da64, N, moduli, B, 1, 4)
+        nt.poly_mul_acc_ntt_rns(acc64, c64, db64, N, moduli, B)
+    got = host32(acc32)
+    assert np.array_equal(got, from_dev(acc64))
+    idx = _idx(N, 262, 6)
+    for p, l in [(0, 0), (200, 3), (511, 7)]:
+        q = moduli[l]
+        s = slice((p * L + l) * N, (p * L + l + 1) * N)
+        prod = oracle.negacyclic_mul_at(a[s], b[s], idx, q)
+        assert np.array_equal(got[s][idx], oracle.eltwise_add(prod, prod, q)), (p, l)
