@@ -52,6 +52,11 @@ def lib():
             ("or_harvey_forward_w", None, [_U64P, _U64, _U64, _U64, ctypes.c_int, ctypes.c_int]),
             ("or_harvey_inverse_w", None, [_U64P, _U64, _U64, _U64, ctypes.c_int, ctypes.c_int]),
             ("or_harvey_fwd_bfly_w", None, [_U64P, _U64P, _U64, _U64, _U64, ctypes.c_int]),
+            ("or_harvey_forward_batch", None, [_U64P, _U64, _U64, _U64, _U64, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_int]),
+            ("or_harvey_inverse_batch", None, [_U64P, _U64, _U64, _U64, _U64, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_int]),
+            ("or_product_batch", None, [_U64P, _U64P, _U64P, _U64, _U64, _U64, _U64, ctypes.c_int]),
         ]:
             f = getattr(L, name)
             f.restype = res
@@ -216,3 +221,84 @@ def harvey_fwd_bfly_w(x0, x1, w, q, bits=64):
     x0, x1 = _arr(x0).copy(), _arr(x1).copy()
     lib().or_harvey_fwd_bfly_w(_p(x0), _p(x1), x0.size, w, q, bits)
     return x0, x1
+
+
+def harvey_forward_batch(a, N, q, psi, out_f=4, bits=64, threads=None):
+    """Forward Harvey model of every length-N limb of `a` (all of modulus q), in a new array."""
+    _check_word(q, bits)
+    a = _arr(a).copy()
+    assert a.size % N == 0
+    lib().or_harvey_forward_batch(_p(a), a.size // N, N, q, psi, out_f, bits, _threads(threads))
+    return a
+
+
+def harvey_inverse_batch(a, N, q, psi, out_f=2, bits=64, threads=None):
+    """Inverse Harvey model (then N^{-1}) of every length-N limb of `a` (all of modulus q)."""
+    _check_word(q, bits)
+    a = _arr(a).copy()
+    assert a.size % N == 0
+    lib().or_harvey_inverse_batch(_p(a), a.size // N, N, q, psi, out_f, bits, _threads(threads))
+    return a
+
+
+def product_batch(a, b, N, q, psi=None, threads=None):
+    """Negacyclic product of every length-N limb pair of a and b (all of modulus q), canonical,
+    through the transforms (O(N log N) per limb); the result does not depend on psi."""
+    a, b = _arr(a), _arr(b)
+    assert a.size == b.size and a.size % N == 0
+    if psi is None:
+        psi = min_root(N, q)
+    c = np.empty_like(a)
+    lib().or_product_batch(_p(c), _p(a), _p(b), a.size // N, N, q, psi, _threads(threads))
+    return c
+
+
+def _limb_rows(x, N, L):
+    """View of a [B][L][N] array as (B, L, N)."""
+    return _arr(x).reshape(-1, L, N)
+
+
+def product_rns(a, b, N, moduli, threads=None):
+    """c = a * b per RNS limb for [B][L][N] operands (limb l of every polynomial mod moduli[l])."""
+    L = len(moduli)
+    A, Bv = _limb_rows(a, N, L), _limb_rows(b, N, L)
+    C = np.empty_like(A)
+    for l, q in enumerate(moduli):
+        C[:, l, :] = product_batch(np.ascontiguousarray(A[:, l, :]), np.ascontiguousarray(Bv[:, l, :]), N, int(q),
+                                   threads=threads).reshape(-1, N)
+    return C.reshape(-1)
+
+
+def forward_rns(a, N, moduli, out_f=1, threads=None):
+    """Forward transform (Harvey model, smallest root) of every limb of a [B][L][N] array; with
+    out_f = 1 the canonical values, which equal the direct definition."""
+    L = len(moduli)
+    A = _limb_rows(a, N, L)
+    C = np.empty_like(A)
+    for l, q in enumerate(moduli):
+        C[:, l, :] = harvey_forward_batch(np.ascontiguousarray(A[:, l, :]), N, int(q), min_root(N, int(q)), out_f,
+                                          threads=threads).reshape(-1, N)
+    return C.reshape(-1)
+
+
+def inverse_rns(a, N, moduli, out_f=1, threads=None):
+    """Inverse transform (Harvey model, smallest root) of every limb of a [B][L][N] array (inputs
+    below 2q); with out_f = 1 the canonical values, which equal the direct definition."""
+    L = len(moduli)
+    A = _limb_rows(a, N, L)
+    C = np.empty_like(A)
+    for l, q in enumerate(moduli):
+        C[:, l, :] = harvey_inverse_batch(np.ascontiguousarray(A[:, l, :]), N, int(q), min_root(N, int(q)), out_f,
+                                          threads=threads).reshape(-1, N)
+    return C.reshape(-1)
+
+
+def add_rns(a, b, N, moduli):
+    """(a + b) mod q_l per limb of [B][L][N] arrays (inputs interpreted mod q_l)."""
+    L = len(moduli)
+    A, Bv = _limb_rows(a, N, L), _limb_rows(b, N, L)
+    C = np.empty_like(A)
+    for l, q in enumerate(moduli):
+        C[:, l, :] = eltwise_add(np.ascontiguousarray(A[:, l, :]).reshape(-1), np.ascontiguousarray(Bv[:, l, :]).reshape(-1),
+                                 int(q)).reshape(-1, N)
+    return C.reshape(-1)

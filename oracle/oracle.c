@@ -28,13 +28,16 @@
  *     positions): out[i] = sum_j a_j psi^{(2 brv(i) + 1) j};
  *   - inverse: out[j] = N^{-1} sum_i A_i psi^{-(2 brv(i) + 1) j}.
  *
- * The Harvey model (or_harvey_*) replays Algorithm 2 with the butterfly of
- * Algorithm 4 and Algorithm 3 with the butterfly of Algorithm 5 at word size
- * beta = 2^64 (or_harvey_forward / _inverse) or beta = 2^32 for moduli below
- * 2^30 (the _w variants), to pin the lazy output ranges the paper states and
- * the representatives a word-size-beta implementation produces.  Its N^{-1}
- * step is one Shoup multiplication of each [0, 2q) value (the paper leaves
- * the representative open).
+ * The Harvey model (or_harvey_*) runs the stages of Algorithm 2 with the
+ * butterfly of Algorithm 4 and those of Algorithm 3 with the butterfly of
+ * Algorithm 5 at word size beta = 2^64 (or_harvey_forward / _inverse) or
+ * beta = 2^32 for moduli below 2^30 (the _w variants), to pin the lazy output
+ * ranges the paper states and the representatives a word-size-beta
+ * implementation produces.  Its N^{-1} step is one Shoup multiplication of each
+ * [0, 2q) value (the paper leaves the representative open).  The _batch forms
+ * run many limbs of one modulus over threads; or_product_batch is the
+ * O(N log N) negacyclic product through these transforms, used where the
+ * O(N^2) schoolbook product would take too long.
  *
  * Parity status: no function here is "parity unpinned"; every one is checked
  * by the CPU tests against closed forms, brute force, an independent big-integer
@@ -320,11 +323,21 @@ void or_negacyclic_mul_at(uint64_t* c, const uint64_t* a, const uint64_t* b, con
   run_schoolbook(c, a, b, idx, count, N, q, nthreads);
 }
 
-/* ---- Harvey model: Algorithms 2-5 replayed at word size beta -------------- */
+/* ---- Harvey model: the lazy transforms at word size beta ----------------- */
 /* Algorithms 4 and 5 are stated for a machine word of size beta (the paper's
  * scalar path uses beta = 2^64, its IFMA path beta = 2^52).  The model takes
  * beta = 2^bits with bits = 64 or 32; beta = 2^32 requires 4q < 2^32.  All
- * "mod beta" arithmetic is unsigned arithmetic masked to bits. */
+ * "mod beta" arithmetic is unsigned arithmetic masked to bits.
+ *
+ * Stage structure (Section 2.2; Algorithms 2 and 3).  A length-N transform is
+ * log2 N stages, one per index bit b.  The stage on bit b combines every
+ * position g whose bit b is clear with its partner g + 2^b, and both
+ * directions take that pair's twiddle from entry k = (N + g) >> (b + 1) of a
+ * table in bit-reversed order: psi^{brv(k)} for the forward, psi^{-brv(k)} for
+ * the inverse.  The forward runs its stages from the top bit down (decimation
+ * in time, bit-reversed output), the inverse from bit 0 up (decimation in
+ * frequency, natural-order output).  Pairs of one stage are independent, so
+ * the order inside a stage does not change any value. */
 
 static uint64_t word_mask(int bits) { return bits == 64 ? ~0ull : ((1ull << bits) - 1); }
 
@@ -354,56 +367,165 @@ static void harvey_inv_bfly(uint64_t* x0, uint64_t* x1, uint64_t w, uint64_t wp,
   *x1 = (w * T - Q * q) & M;                   /* arithmetic mod beta */
 }
 
-/* Algorithm 2 (Cooley-Tukey, merged psi) with Algorithm 4 butterflies at word
- * size 2^bits, in place.  Input values must be < 4q.  out_f = 4 leaves
- * [0, 4q); out_f = 1 reduces to [0, q) by conditional subtraction of 2q then q. */
-void or_harvey_forward_w(uint64_t* a, uint64_t N, uint64_t q, uint64_t psi, int out_f, int bits) {
-  const int logn = ilog2(N);
-  uint64_t* psi_rev = (uint64_t*)malloc(sizeof(uint64_t) * N);
-  for (uint64_t k = 0; k < N; ++k) psi_rev[k] = or_powmod(psi, or_brv(k, logn), q);
-  uint64_t t = N;
-  for (uint64_t m = 1; m < N; m *= 2) {
-    t /= 2;
-    for (uint64_t i = 0; i < m; ++i) {
-      uint64_t j1 = 2 * i * t, w = psi_rev[m + i], wp = shoup_precon_w(w, q, bits);
-      for (uint64_t j = j1; j < j1 + t; ++j) harvey_fwd_bfly(&a[j], &a[j + t], w, wp, q, bits);
+/* Twiddles of one direction for (N, q): w[k] = r^{brv(k)} with r = psi
+ * (forward) or psi^{-1} (inverse), and their companions at word size 2^bits. */
+typedef struct {
+  uint64_t N, q;
+  int logn, bits, out_f;
+  uint64_t *w, *wp;
+  uint64_t ninv, ninvp;
+} hv_plan_t;
+
+static void hv_plan_init(hv_plan_t* p, uint64_t N, uint64_t q, uint64_t psi, int inverse, int out_f, int bits) {
+  p->N = N; p->q = q; p->logn = ilog2(N); p->bits = bits; p->out_f = out_f;
+  const uint64_t r = inverse ? or_invmod(psi, q) : psi;
+  uint64_t* pw = (uint64_t*)malloc(sizeof(uint64_t) * N);      /* pw[e] = r^e, e < N */
+  pw[0] = 1 % q;
+  for (uint64_t e = 1; e < N; ++e) pw[e] = or_mulmod(pw[e - 1], r, q);
+  p->w = (uint64_t*)malloc(sizeof(uint64_t) * N);
+  p->wp = (uint64_t*)malloc(sizeof(uint64_t) * N);
+  for (uint64_t k = 0; k < N; ++k) {
+    p->w[k] = pw[or_brv(k, p->logn)];
+    p->wp[k] = shoup_precon_w(p->w[k], q, bits);
+  }
+  free(pw);
+  p->ninv = or_invmod(N % q, q);
+  p->ninvp = shoup_precon_w(p->ninv, q, bits);
+}
+
+static void hv_plan_free(hv_plan_t* p) { free(p->w); free(p->wp); }
+
+/* Forward transform of one limb in place (Algorithm 2 with Algorithm 4
+ * butterflies).  Input values must be < 4q.  out_f = 4 leaves [0, 4q);
+ * out_f = 1 reduces to [0, q) by conditional subtraction of 2q then q. */
+static void hv_forward_limb(uint64_t* a, const hv_plan_t* p) {
+  const uint64_t N = p->N, q = p->q;
+  for (int b = p->logn - 1; b >= 0; --b) {
+    const uint64_t half = 1ull << b;
+    for (uint64_t g = 0; g < N; ++g) {
+      if (g & half) continue;
+      const uint64_t k = (N + g) >> (b + 1);
+      harvey_fwd_bfly(&a[g], &a[g + half], p->w[k], p->wp[k], q, p->bits);
     }
   }
-  if (out_f == 1) {
+  if (p->out_f == 1) {
     for (uint64_t j = 0; j < N; ++j) {
       if (a[j] >= 2 * q) a[j] -= 2 * q;
       if (a[j] >= q) a[j] -= q;
     }
   }
-  free(psi_rev);
 }
 
-/* Algorithm 3 (Gentleman-Sande) with Algorithm 5 butterflies at word size
- * 2^bits, then the multiplication by N^{-1}, in place.  Input values must be
- * < 2q.  out_f = 2 leaves [0, 2q); out_f = 1 reduces to [0, q). */
-void or_harvey_inverse_w(uint64_t* a, uint64_t N, uint64_t q, uint64_t psi, int out_f, int bits) {
-  const int logn = ilog2(N);
-  const uint64_t M = word_mask(bits);
-  uint64_t psi_inv = or_invmod(psi, q);
-  uint64_t* inv_rev = (uint64_t*)malloc(sizeof(uint64_t) * N);
-  for (uint64_t k = 0; k < N; ++k) inv_rev[k] = or_powmod(psi_inv, or_brv(k, logn), q);
-  uint64_t t = 1;
-  for (uint64_t m = N; m > 1; m /= 2) {
-    uint64_t j1 = 0, h = m / 2;
-    for (uint64_t i = 0; i < h; ++i) {
-      uint64_t w = inv_rev[h + i], wp = shoup_precon_w(w, q, bits);
-      for (uint64_t j = j1; j < j1 + t; ++j) harvey_inv_bfly(&a[j], &a[j + t], w, wp, q, bits);
-      j1 += 2 * t;
+/* Inverse transform of one limb in place (Algorithm 3 with Algorithm 5
+ * butterflies), then each value times N^{-1} by one Shoup multiplication.
+ * Input values must be < 2q.  out_f = 2 leaves [0, 2q); out_f = 1 reduces to
+ * [0, q). */
+static void hv_inverse_limb(uint64_t* a, const hv_plan_t* p) {
+  const uint64_t N = p->N, q = p->q, M = word_mask(p->bits);
+  for (int b = 0; b < p->logn; ++b) {
+    const uint64_t half = 1ull << b;
+    for (uint64_t g = 0; g < N; ++g) {
+      if (g & half) continue;
+      const uint64_t k = (N + g) >> (b + 1);
+      harvey_inv_bfly(&a[g], &a[g + half], p->w[k], p->wp[k], q, p->bits);
     }
-    t *= 2;
   }
-  uint64_t ninv = or_invmod(N % q, q), ninvp = shoup_precon_w(ninv, q, bits);
   for (uint64_t j = 0; j < N; ++j) {
-    uint64_t Q = (uint64_t)(((u128)ninvp * a[j]) >> bits);
-    a[j] = (ninv * a[j] - Q * q) & M;          /* [0, 2q) */
-    if (out_f == 1 && a[j] >= q) a[j] -= q;
+    uint64_t Q = (uint64_t)(((u128)p->ninvp * a[j]) >> p->bits);
+    a[j] = (p->ninv * a[j] - Q * q) & M;        /* [0, 2q) */
+    if (p->out_f == 1 && a[j] >= q) a[j] -= q;
   }
-  free(inv_rev);
+}
+
+/* Work over `count` limbs of one modulus, spread over threads. */
+typedef struct {
+  int op;                                       /* 0 forward, 1 inverse, 2 product */
+  uint64_t* a; const uint64_t* b; uint64_t* c;
+  const hv_plan_t* fwd; const hv_plan_t* inv;
+  uint64_t lo, hi;
+} hv_job_t;
+
+/* The negacyclic product of one limb through the transforms: the product
+ * listing of Section 4 (forward of both factors, element-wise product mod q,
+ * inverse), c = a * b mod (X^N + 1, q), canonical. */
+static void hv_product_limb(uint64_t* c, const uint64_t* a, const uint64_t* b, uint64_t* tmp,
+                            const hv_plan_t* fwd, const hv_plan_t* inv) {
+  const uint64_t N = fwd->N, q = fwd->q;
+  for (uint64_t j = 0; j < N; ++j) { c[j] = a[j] % q; tmp[j] = b[j] % q; }
+  hv_forward_limb(c, fwd);
+  hv_forward_limb(tmp, fwd);
+  for (uint64_t j = 0; j < N; ++j) c[j] = or_mulmod(c[j] % q, tmp[j] % q, q);
+  hv_inverse_limb(c, inv);
+}
+
+static void* hv_worker(void* arg) {
+  hv_job_t* jb = (hv_job_t*)arg;
+  const uint64_t N = jb->fwd ? jb->fwd->N : jb->inv->N;
+  uint64_t* tmp = jb->op == 2 ? (uint64_t*)malloc(sizeof(uint64_t) * N) : NULL;
+  for (uint64_t l = jb->lo; l < jb->hi; ++l) {
+    if (jb->op == 0) hv_forward_limb(jb->a + l * N, jb->fwd);
+    else if (jb->op == 1) hv_inverse_limb(jb->a + l * N, jb->inv);
+    else hv_product_limb(jb->c + l * N, jb->a + l * N, jb->b + l * N, tmp, jb->fwd, jb->inv);
+  }
+  free(tmp);
+  return NULL;
+}
+
+static void hv_run(hv_job_t base, uint64_t count, int nthreads) {
+  if (nthreads < 1) nthreads = 1;
+  if ((uint64_t)nthreads > count) nthreads = (int)(count ? count : 1);
+  hv_job_t* jobs = (hv_job_t*)malloc(sizeof(hv_job_t) * nthreads);
+  pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * nthreads);
+  for (int t = 0; t < nthreads; ++t) {
+    jobs[t] = base;
+    jobs[t].lo = count * t / nthreads;
+    jobs[t].hi = count * (t + 1) / nthreads;
+    pthread_create(&th[t], NULL, hv_worker, &jobs[t]);
+  }
+  for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+  free(th); free(jobs);
+}
+
+/* `count` limbs a[count][N] of modulus q, transformed in place at word size
+ * 2^bits: forward with out_f in {1, 4}, inverse with out_f in {1, 2}. */
+void or_harvey_forward_batch(uint64_t* a, uint64_t count, uint64_t N, uint64_t q, uint64_t psi, int out_f,
+                             int bits, int nthreads) {
+  hv_plan_t p;
+  hv_plan_init(&p, N, q, psi, 0, out_f, bits);
+  hv_job_t jb = {0, a, NULL, NULL, &p, NULL, 0, 0};
+  hv_run(jb, count, nthreads);
+  hv_plan_free(&p);
+}
+void or_harvey_inverse_batch(uint64_t* a, uint64_t count, uint64_t N, uint64_t q, uint64_t psi, int out_f,
+                             int bits, int nthreads) {
+  hv_plan_t p;
+  hv_plan_init(&p, N, q, psi, 1, out_f, bits);
+  hv_job_t jb = {1, a, NULL, NULL, NULL, &p, 0, 0};
+  hv_run(jb, count, nthreads);
+  hv_plan_free(&p);
+}
+
+/* c[l] = a[l] * b[l] mod (X^N + 1, q) for each of `count` limbs [count][N],
+ * through the transforms (the product listing of Section 4), canonical; inputs
+ * are interpreted mod q.  O(N log N) per limb; the schoolbook product
+ * (or_negacyclic_mul) is the definition it is checked against. */
+void or_product_batch(uint64_t* c, const uint64_t* a, const uint64_t* b, uint64_t count, uint64_t N, uint64_t q,
+                      uint64_t psi, int nthreads) {
+  hv_plan_t pf, pi;
+  hv_plan_init(&pf, N, q, psi, 0, 4, 64);
+  hv_plan_init(&pi, N, q, psi, 1, 1, 64);
+  hv_job_t jb = {2, (uint64_t*)a, b, c, &pf, &pi, 0, 0};
+  hv_run(jb, count, nthreads);
+  hv_plan_free(&pf);
+  hv_plan_free(&pi);
+}
+
+/* Single limb at word size 2^bits (forward: values < 4q in; inverse: < 2q). */
+void or_harvey_forward_w(uint64_t* a, uint64_t N, uint64_t q, uint64_t psi, int out_f, int bits) {
+  or_harvey_forward_batch(a, 1, N, q, psi, out_f, bits, 1);
+}
+void or_harvey_inverse_w(uint64_t* a, uint64_t N, uint64_t q, uint64_t psi, int out_f, int bits) {
+  or_harvey_inverse_batch(a, 1, N, q, psi, out_f, bits, 1);
 }
 
 /* The scalar path of the paper: beta = 2^64. */

@@ -12,7 +12,10 @@ other than their own formulas:
 * the schoolbook product against full polynomial multiplication followed by
   reduction with X^N = -1, and against special products (by 1, by X, X^{N/2}^2);
 * a second algorithm: the Harvey model (Algorithms 2+4 and 3+5) must agree with
-  the direct O(N^2) sums, and stay inside the lazy ranges of Algorithms 4 and 5.
+  the direct O(N^2) sums, and stay inside the lazy ranges of Algorithms 4 and 5;
+* its batched forms (many limbs of one modulus on threads, and the O(N log N)
+  product through the transforms) limb by limb against the direct sums and the
+  schoolbook product, plus the special products X^(N/2) X^(N/2) = -1 and a X.
 """
 import itertools
 import json
@@ -292,3 +295,86 @@ def test_harvey_butterfly_brute_force(bits, golden_primes):
                 T = int(y0[i]) - A
                 assert 0 <= T < 2 * q and T % q == (w * X1) % q, (q, w, X0, X1)
                 assert int(y1[i]) == A + 2 * q - T and int(y0[i]) < 4 * q and int(y1[i]) < 4 * q
+
+
+# ---- batched forms (many limbs of one modulus, threads) ------------------------
+
+@pytest.mark.parametrize("logn", [1, 3, 7, 9])
+def test_product_batch_matches_schoolbook(logn, golden_primes):
+    """The O(N log N) product through the transforms (Section 4 product listing) equals the
+    schoolbook negacyclic product of Section 2 on every limb, for lazy inputs up to 4q and for
+    edge moduli (the smallest 50- and 62-bit NTT primes, a 30-bit one)."""
+    N = 1 << logn
+    primes = [golden_primes["rns_16384"]["moduli"][0], golden_primes["large_65536"]["moduli"][3],
+              golden_primes["edge"]["by_bits"]["62"][0], golden_primes["edge"]["by_bits"]["50"][1],
+              golden_primes["edge"]["by_bits"]["30"][0]]
+    for q in primes:
+        count = 5
+        a = np.concatenate([lazy_mod(unit_seed(50, logn, q, k), N, q, 4) for k in range(count)])
+        b = np.concatenate([uniform_mod(unit_seed(51, logn, q, k), N, q) for k in range(count)])
+        c = oracle.product_batch(a, b, N, q, threads=3)
+        for k in range(count):
+            s = slice(k * N, (k + 1) * N)
+            assert np.array_equal(c[s], oracle.negacyclic_mul(a[s], b[s], q)), (q, k)
+
+
+def test_product_batch_special_products(golden_primes):
+    """X^(N/2) * X^(N/2) = -1 and a * X = the negacyclic shift of a, limb by limb."""
+    N, q = 1024, golden_primes["single_1024"]["moduli"][0]
+    half = np.zeros(N, dtype=np.uint64)
+    half[N // 2] = 1
+    x = np.zeros(N, dtype=np.uint64)
+    x[1] = 1
+    a = uniform_mod(unit_seed(52), N, q)
+    c = oracle.product_batch(np.concatenate([half, a]), np.concatenate([half, x]), N, q)
+    minus_one = np.zeros(N, dtype=np.uint64)
+    minus_one[0] = q - 1
+    assert np.array_equal(c[:N], minus_one)
+    shifted = np.concatenate([[(q - int(a[-1])) % q], a[:-1]]).astype(np.uint64)
+    assert np.array_equal(c[N:], shifted)
+
+
+@pytest.mark.parametrize("logn", [2, 5, 10])
+def test_harvey_batch_matches_direct(logn, golden_primes):
+    """Every limb of the batched Harvey forward/inverse reduces to the direct O(N^2) sums, and
+    the lazy words stay in [0, 4q) / [0, 2q); the canonical form equals the sums exactly."""
+    N = 1 << logn
+    for q in [golden_primes["single_1024"]["moduli"][0], golden_primes["edge"]["by_bits"]["61"][0]]:
+        psi = oracle.min_root(N, q)
+        count = 4
+        a = np.concatenate([lazy_mod(unit_seed(53, logn, q, k), N, q, 4) for k in range(count)])
+        A = np.concatenate([lazy_mod(unit_seed(54, logn, q, k), N, q, 2) for k in range(count)])
+        lazy = oracle.harvey_forward_batch(a, N, q, psi, 4, threads=2)
+        canon = oracle.harvey_forward_batch(a, N, q, psi, 1, threads=2)
+        ilazy = oracle.harvey_inverse_batch(A, N, q, psi, 2, threads=2)
+        icanon = oracle.harvey_inverse_batch(A, N, q, psi, 1, threads=2)
+        assert np.all(lazy < np.uint64(4 * q)) and np.all(ilazy < np.uint64(2 * q))
+        for k in range(count):
+            s = slice(k * N, (k + 1) * N)
+            ref = oracle.ntt_forward(a[s], q, psi)
+            iref = oracle.ntt_inverse(A[s], q, psi)
+            assert np.array_equal(canon[s], ref) and np.array_equal(lazy[s] % np.uint64(q), ref)
+            assert np.array_equal(icanon[s], iref) and np.array_equal(ilazy[s] % np.uint64(q), iref)
+
+
+def test_rns_helpers_use_each_limbs_modulus(golden_primes):
+    """product_rns / forward_rns / inverse_rns / add_rns on a [B][L][N] array treat limb l of
+    every polynomial modulo moduli[l] (checked limb by limb against the schoolbook product and
+    the direct sums)."""
+    N = 64
+    moduli = golden_primes["rns_16384"]["moduli"][:3]
+    B, L = 2, len(moduli)
+    a = np.concatenate([uniform_mod(unit_seed(55, p, l), N, q) for p in range(B) for l, q in enumerate(moduli)])
+    b = np.concatenate([uniform_mod(unit_seed(56, p, l), N, q) for p in range(B) for l, q in enumerate(moduli)])
+    c = oracle.product_rns(a, b, N, moduli)
+    f = oracle.forward_rns(a, N, moduli)
+    i = oracle.inverse_rns(a, N, moduli)
+    s_ = oracle.add_rns(a, b, N, moduli)
+    for p in range(B):
+        for l, q in enumerate(moduli):
+            s = slice((p * L + l) * N, (p * L + l + 1) * N)
+            psi = oracle.min_root(N, q)
+            assert np.array_equal(c[s], oracle.negacyclic_mul(a[s], b[s], q))
+            assert np.array_equal(f[s], oracle.ntt_forward(a[s], q, psi))
+            assert np.array_equal(i[s], oracle.ntt_inverse(a[s], q, psi))
+            assert np.array_equal(s_[s], oracle.eltwise_add(a[s], b[s], q))
