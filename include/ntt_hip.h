@@ -477,8 +477,15 @@ ntt_status ntt_set_variant(uint64_t N, uint64_t num_items, int forward, int vari
  * ntt_server_read: enqueues on `stream` a copy of a completed request's
  *   result into dst (device, L * N words); NTT_EBUSY before completion, the
  *   request's own status if it failed, NTT_ENOTFOUND without a kept result.
- * ntt_server_release: frees a completed request's result and record
- *   (NTT_EBUSY while it is still queued or running).
+ *   The server records an event after the copy on `stream`.
+ * ntt_server_release: drops a completed request's record and returns its
+ *   result's arena range (NTT_EBUSY while it is still queued or running).  A
+ *   range read with ntt_server_read goes back to the arena only once every
+ *   such copy has completed on its stream, so read-then-release needs no
+ *   synchronisation in between.  Uses of info.result made by the caller's own
+ *   kernels are not tracked: release after they have completed.  A request
+ *   whose launch failed part way keeps its ranges until the kernels already
+ *   enqueued for it have drained.
  * ntt_server_destroy: requests not yet launched fail with NTT_EBUSY, launches
  *   in flight are waited for, then the arena and streams are freed.
  */

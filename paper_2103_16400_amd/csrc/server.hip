@@ -106,6 +106,15 @@ struct Req {
   bool has_out = false, has_tmp = false, deferred = false;
   uint32_t state = NTT_REQ_WAITING;
   ntt_status status = NTT_OK;
+  std::vector<hipEvent_t> read_events;   // one per ntt_server_read: the copy's completion on the caller's stream
+};
+
+// Arena ranges whose last users are still on the device: freed once every
+// event has completed (reads on callers' streams, or a failed request's
+// already-enqueued kernels).
+struct PendingFree {
+  std::vector<hipEvent_t> events;
+  uint64_t off[2] = {0, 0}, len[2] = {0, 0};
 };
 
 struct LaterArrival {
@@ -150,6 +159,7 @@ struct ntt_server {
   std::vector<Slot> slots;
   std::deque<std::pair<hipEvent_t, Req*>> fifo_inflight;
   std::vector<hipEvent_t> event_pool;
+  std::vector<PendingFree> pending_free;
   std::vector<BatchTask> tasks;
   ntt_server_stats st{};
 };
@@ -186,15 +196,62 @@ void drop_out(ntt_server* s, Req* r) {
   r->has_out = false;
 }
 
-void finish(ntt_server* s, Req* r, int64_t t, ntt_status status) {
+hipEvent_t take_event(ntt_server* s);
+
+// Frees the request's arena ranges once `stream` has drained the work already
+// enqueued on it (an event, or a synchronisation when no event can be had).
+void free_after(ntt_server* s, Req* r, hipStream_t stream) {
+  PendingFree pf;
+  int k = 0;
+  if (r->has_out) { pf.off[k] = r->out_off; pf.len[k++] = r->out_len; }
+  if (r->has_tmp) { pf.off[k] = r->tmp_off; pf.len[k++] = r->tmp_len; }
+  r->has_out = r->has_tmp = false;
+  if (!k) return;
+  hipEvent_t ev = take_event(s);
+  if (ev && hipEventRecord(ev, stream) == hipSuccess) {
+    pf.events.push_back(ev);
+    s->pending_free.push_back(std::move(pf));
+    return;
+  }
+  if (ev) s->event_pool.push_back(ev);
+  (void)hipStreamSynchronize(stream);
+  for (int i = 0; i < k; ++i) s->arena.release(pf.off[i], pf.len[i]);
+}
+
+// stream: where the request's kernels were enqueued when a launch failed part
+// way (nullptr when nothing of it reached the device, or on completion).
+void finish(ntt_server* s, Req* r, int64_t t, ntt_status status, hipStream_t stream = nullptr) {
   r->done = t;
   r->status = status;
   r->state = status == NTT_OK ? NTT_REQ_DONE : NTT_REQ_FAILED;
-  drop_tmp(s, r);
-  if (status != NTT_OK || s->cfg.release_on_completion) drop_out(s, r);
+  if (status != NTT_OK && stream) {
+    free_after(s, r, stream);        // earlier launches of this request may still write its ranges
+  } else {
+    drop_tmp(s, r);
+    if (status != NTT_OK || s->cfg.release_on_completion) drop_out(s, r);
+  }
   if (status == NTT_OK) ++s->st.completed;
   else ++s->st.failed;
   --s->outstanding;
+}
+
+// Returns the ranges whose events have all completed to the arena.
+bool reap_frees(ntt_server* s) {
+  bool any = false;
+  for (size_t i = 0; i < s->pending_free.size();) {
+    PendingFree& pf = s->pending_free[i];
+    bool done = true;
+    for (hipEvent_t e : pf.events)
+      if (hipEventQuery(e) == hipErrorNotReady) { done = false; break; }
+    if (!done) { ++i; continue; }
+    for (int k = 0; k < 2; ++k)
+      if (pf.len[k]) s->arena.release(pf.off[k], pf.len[k]);
+    for (hipEvent_t e : pf.events) s->event_pool.push_back(e);
+    pf = std::move(s->pending_free.back());
+    s->pending_free.pop_back();
+    any = true;
+  }
+  return any;
 }
 
 void admit(ntt_server* s) {
@@ -319,7 +376,7 @@ bool launch(ntt_server* s) {
       if (!e && (!ev || hipEventRecord(ev, ws) != hipSuccess)) e = NTT_EDEVICE;
       if (e) {
         if (ev) s->event_pool.push_back(ev);
-        finish(s, r, clock_ns(), e);
+        finish(s, r, clock_ns(), e, ws);
         s->cv_done.notify_all();
         continue;
       }
@@ -364,7 +421,7 @@ bool launch(ntt_server* s) {
       ntt_status e = batch_launch_tasks(sl.batch, s->tasks.data(), s->tasks.size(), sl.stream, s->cfg.use_graph != 0);
       if (e == NTT_OK && hipEventRecord(sl.event, sl.stream) != hipSuccess) e = NTT_EDEVICE;
       if (e) {
-        for (Req* r : sl.reqs) finish(s, r, clock_ns(), e);
+        for (Req* r : sl.reqs) finish(s, r, clock_ns(), e, sl.stream);
         sl.reqs.clear();
         s->cv_done.notify_all();
         continue;
@@ -387,7 +444,7 @@ bool launch(ntt_server* s) {
     if (!e && (!ev || hipEventRecord(ev, stream) != hipSuccess)) e = NTT_EDEVICE;
     if (e) {
       if (ev) s->event_pool.push_back(ev);
-      finish(s, r, clock_ns(), e);
+      finish(s, r, clock_ns(), e, stream);
       s->cv_done.notify_all();
       continue;
     }
@@ -434,11 +491,11 @@ bool reap(ntt_server* s) {
     any = true;
   }
   if (any) s->cv_done.notify_all();
-  return any;
+  return reap_frees(s) || any;
 }
 
 bool in_flight(const ntt_server* s) {
-  if (!s->fifo_inflight.empty() || !s->wide_inflight.empty()) return true;
+  if (!s->fifo_inflight.empty() || !s->wide_inflight.empty() || !s->pending_free.empty()) return true;
   for (const Slot& sl : s->slots)
     if (sl.busy) return true;
   return false;
@@ -514,6 +571,17 @@ void destroy_resources(ntt_server* s) {
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
   }
   for (hipStream_t w : s->wide) (void)hipStreamDestroy(w);
+  for (PendingFree& pf : s->pending_free)
+    for (hipEvent_t e : pf.events) {
+      (void)hipEventSynchronize(e);
+      (void)hipEventDestroy(e);
+    }
+  s->pending_free.clear();
+  for (auto& kv : s->records)
+    for (hipEvent_t e : kv.second->read_events) {
+      (void)hipEventSynchronize(e);
+      (void)hipEventDestroy(e);
+    }
   for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
   if (s->base) (void)hipFree(s->base);
 }
@@ -690,14 +758,22 @@ ntt_status ntt_server_read(ntt_server* s, uint64_t ticket, uint64_t* dst, ntt_st
   std::lock_guard<std::mutex> g(s->mu);
   auto it = s->records.find(ticket);
   if (it == s->records.end()) return NTT_ENOTFOUND;
-  const Req* r = it->second.get();
+  Req* r = it->second.get();
   if (r->state == NTT_REQ_FAILED) return r->status;
   if (r->state != NTT_REQ_DONE) return NTT_EBUSY;
   if (!r->has_out) return NTT_ENOTFOUND;
   const size_t bytes = (size_t)r->L * r->N * sizeof(uint64_t);
+  hipEvent_t ev = take_event(s);
+  if (!ev) return NTT_EDEVICE;
   if (hipMemcpyAsync(dst, s->base + r->out_off / sizeof(uint64_t), bytes, hipMemcpyDeviceToDevice,
-                     (hipStream_t)stream) != hipSuccess)
+                     (hipStream_t)stream) != hipSuccess ||
+      hipEventRecord(ev, (hipStream_t)stream) != hipSuccess) {
+    // a copy that did reach the stream has run once this returns
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    s->event_pool.push_back(ev);
     return NTT_EDEVICE;
+  }
+  r->read_events.push_back(ev);       // release frees the range only after this copy has run
   return NTT_OK;
 }
 
@@ -708,7 +784,19 @@ ntt_status ntt_server_release(ntt_server* s, uint64_t ticket) {
   if (it == s->records.end()) return NTT_ENOTFOUND;
   Req* r = it->second.get();
   if (r->state != NTT_REQ_DONE && r->state != NTT_REQ_FAILED) return NTT_EBUSY;
-  drop_out(s, r);
+  if (r->has_out && !r->read_events.empty()) {
+    // copies enqueued by ntt_server_read may not have run yet: the scheduler frees the
+    // range once they have, so a request admitted into it cannot overwrite them
+    PendingFree pf;
+    pf.events.swap(r->read_events);
+    pf.off[0] = r->out_off;
+    pf.len[0] = r->out_len;
+    r->has_out = false;
+    s->pending_free.push_back(std::move(pf));
+  } else {
+    drop_out(s, r);
+    for (hipEvent_t e : r->read_events) s->event_pool.push_back(e);
+  }
   s->records.erase(it);
   s->cv_work.notify_one();
   return NTT_OK;

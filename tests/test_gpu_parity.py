@@ -45,11 +45,34 @@ def _fwd_check(out, a, q, psi, out_f, full=True, idx=None):
     else:
         ref = oracle.ntt_forward_at(a, idx, q, psi)
         assert np.array_equal(out[idx] % np.uint64(q), ref)
+        assert np.array_equal(out % np.uint64(q), oracle.harvey_forward(a, q, psi, 1))
 
 
 def _sample_idx(N, seed, k=48):
     r = uniform_mod(unit_seed(seed, N), k, N).astype(np.uint64)
     return np.unique(np.concatenate([r, np.array([0, 1, N // 2, N - 1], dtype=np.uint64)]))
+
+
+def _prod_ref(a, b, q):
+    """Canonical negacyclic product of one limb: the schoolbook definition (Section 2) up to
+    N = 1024, above that the oracle's O(N log N) pipeline through its transforms (the product
+    listing of Section 4), which CPU tests pin to the schoolbook product."""
+    if a.size <= 1024:
+        return oracle.negacyclic_mul(a, b, q)
+    return oracle.product_batch(a, b, a.size, q)
+
+
+def _fwd_canon(a, q):
+    """Canonical forward transform of one limb (inputs below 4q): direct sums up to N = 1024,
+    above that the Harvey model with a final correction (pinned to the direct sums)."""
+    psi = oracle.min_root(a.size, q)
+    return oracle.ntt_forward(a, q, psi) if a.size <= 1024 else oracle.harvey_forward(a, q, psi, 1)
+
+
+def _inv_canon(A, q):
+    """Canonical inverse transform of one limb (inputs below 2q), as _fwd_canon."""
+    psi = oracle.min_root(A.size, q)
+    return oracle.ntt_inverse(A, q, psi) if A.size <= 1024 else oracle.harvey_inverse(A, q, psi, 1)
 
 
 # ---------------------------------------------------------------- element-wise
@@ -274,6 +297,7 @@ def test_explicit_root_plans(nt):
         else:
             idx = _sample_idx(N, 31)
             assert np.array_equal(out[idx], oracle.ntt_forward_at(a, idx, q, psi))
+            assert np.array_equal(out, oracle.harvey_forward(a, q, psi, 1))
         plan.inverse(o, o, 1, 1)
         assert np.array_equal(from_dev(o), a)
         plan.close()
@@ -334,6 +358,8 @@ def test_two_pass_schedule_variants(nt, logN):
     ref_fwd = [oracle.ntt_forward_at(a[l * N:(l + 1) * N], idx, q, psis[l]) for l, q in enumerate(moduli)]
     harvey0 = oracle.harvey_forward(a[:N], moduli[0], psis[0], 4)
     ref_inv = [oracle.ntt_inverse_at(A[l * N:(l + 1) * N], idx, q, psis[l]) for l, q in enumerate(moduli)]
+    full_fwd = [oracle.harvey_forward(a[l * N:(l + 1) * N], q, psis[l], 1) for l, q in enumerate(moduli)]
+    full_inv = [oracle.harvey_inverse(A[l * N:(l + 1) * N], q, psis[l], 1) for l, q in enumerate(moduli)]
     nv = _variant_count(nt, N)
     assert nv >= 5
     ws = empty_dev(L * N)
@@ -350,6 +376,7 @@ def test_two_pass_schedule_variants(nt, logN):
             for l, q in enumerate(moduli):
                 s = slice(l * N, (l + 1) * N)
                 assert np.array_equal(canon[s][idx], ref_fwd[l]), (v, l)
+                assert np.array_equal(canon[s], full_fwd[l]), (v, l)
                 assert np.array_equal(canon[s], lazy[s] % np.uint64(q)), (v, l)
             dm = to_dev(m)
             nt.ntt_forward_mul_rns(dm, da, dm, N, moduli, 1, 4, ws)
@@ -362,6 +389,7 @@ def test_two_pass_schedule_variants(nt, logN):
             inv = from_dev(dout)
             for l, q in enumerate(moduli):
                 assert np.array_equal(inv[l * N:(l + 1) * N][idx], ref_inv[l]), (v, l)
+                assert np.array_equal(inv[l * N:(l + 1) * N], full_inv[l]), (v, l)
             dacc = to_dev(acc0)
             nt.ntt_inverse_acc_rns(dacc, dA, N, moduli, 1, 2, ws)
             assert np.array_equal(from_dev(dacc), np.concatenate(
@@ -382,19 +410,20 @@ def test_rns_forward_inverse(nt, key, B):
     nt.ntt_forward_rns(o, d, N, moduli, B, 1, 4)
     out = from_dev(o)
     idx = _sample_idx(N, 41, 16)
+    exact = lazy_words_exact(nt, N, moduli)
     for p in range(B):
         for l, q in enumerate(moduli):
             seg = out[(p * L + l) * N:(p * L + l + 1) * N]
             src = a[(p * L + l) * N:(p * L + l + 1) * N]
             assert np.all(seg < np.uint64(4 * q))
             psi = PRIMES[key]["psi"][l]
-            assert np.array_equal(seg[idx] % np.uint64(q), oracle.ntt_forward_at(src, idx, q, psi))
             if l in (0, L - 1):
-                model = oracle.harvey_forward(src, q, psi, 4)
-                if lazy_words_exact(nt, N, moduli):
-                    assert np.array_equal(seg, model)
-                else:
-                    assert np.array_equal(seg % np.uint64(q), model % np.uint64(q))
+                assert np.array_equal(seg[idx] % np.uint64(q), oracle.ntt_forward_at(src, idx, q, psi))
+            model = oracle.harvey_forward(src, q, psi, 4)
+            if exact:
+                assert np.array_equal(seg, model), (p, l)
+            else:
+                assert np.array_equal(seg % np.uint64(q), model % np.uint64(q)), (p, l)
     # lazy [0, 4q) is not a legal inverse input: reduce on the host first
     canon = to_dev(np.concatenate([
         out[(p * L + l) * N:(p * L + l + 1) * N] % np.uint64(q)
@@ -442,9 +471,8 @@ def test_poly_mul_rns(nt, logN, L, B):
     for p in range(B):
         for l, q in enumerate(moduli):
             s = slice((p * L + l) * N, (p * L + l + 1) * N)
-            if N <= 1024:
-                assert np.array_equal(out[s], oracle.negacyclic_mul(a[s], b[s], q))
-            else:
+            assert np.array_equal(out[s], _prod_ref(a[s], b[s], q)), (p, l)
+            if N > 1024:
                 assert np.array_equal(out[s][idx], oracle.negacyclic_mul_at(a[s], b[s], idx, q))
     # in place: result == a
     da = to_dev(a)
@@ -486,19 +514,13 @@ def test_product_multiply_edges(nt, logN, bits):
     dprod = empty_dev(N * L)
     nt.ntt_forward_mul_rns(dprod, to_dev(b), to_dev(m), N, moduli, 1)
     prod = from_dev(dprod)
-    idx = _sample_idx(N, 98, 16)
     for l, q in enumerate(moduli):
         s = slice(l * N, (l + 1) * N)
-        psi = oracle.min_root(N, q)
-        fb = oracle.ntt_forward(b[s], q, psi)
+        fb = _fwd_canon(b[s], q)
         pm = oracle.eltwise_mult(fb, m[s] % np.uint64(q), q)
         assert np.array_equal(prod[s], pm), ("fwd_mul", bits, l)
-        if N <= 1024:
-            want = oracle.eltwise_add(acc0[s], oracle.ntt_inverse(pm, q, psi), q)
-            assert np.array_equal(got[s], want), ("product", bits, l)
-        else:
-            want = oracle.eltwise_add(acc0[s][idx], oracle.ntt_inverse_at(pm, idx, q, psi), q)
-            assert np.array_equal(got[s][idx], want), ("product", bits, l)
+        want = oracle.eltwise_add(acc0[s], _inv_canon(pm, q), q)
+        assert np.array_equal(got[s], want), ("product", bits, l)
 
 
 @pytest.mark.parametrize("logN,L,B", [(1, 1, 2), (6, 2, 2), (10, 3, 2), (12, 4, 1), (13, 2, 2), (14, 8, 2),
@@ -517,16 +539,11 @@ def test_poly_mul_acc_ntt(nt, logN, L, B):
     ws = empty_dev(2 * a.size) if N > (1 << 14) else None
     nt.poly_mul_acc_ntt_rns(dacc, a_ntt, to_dev(b), N, moduli, B, ws)
     got = from_dev(dacc)
-    idx = _sample_idx(N, 93, 12)
     for p in range(B):
         for l, q in enumerate(moduli):
             s = slice((p * L + l) * N, (p * L + l + 1) * N)
-            if N <= 2048:
-                ref = oracle.eltwise_add(acc0[s], oracle.negacyclic_mul(a[s], b[s], q), q)
-                assert np.array_equal(got[s], ref), (p, l)
-            else:
-                ref = oracle.eltwise_add(acc0[s][idx], oracle.negacyclic_mul_at(a[s], b[s], idx, q), q)
-                assert np.array_equal(got[s][idx], ref), (p, l)
+            ref = oracle.eltwise_add(acc0[s], _prod_ref(a[s], b[s], q), q)
+            assert np.array_equal(got[s], ref), (p, l)
     # and the same words as the three-step form through the public entry points
     dacc2 = to_dev(acc0)
     ws2 = empty_dev(2 * a.size)
@@ -555,16 +572,13 @@ def test_fused_forward_mul_and_inverse_acc(nt, logN, L, B):
     for p in range(B):
         for l, q in enumerate(moduli):
             s = slice((p * L + l) * N, (p * L + l + 1) * N)
-            if N <= 4096:
-                fa = oracle.ntt_forward(a[s], q, psis[q])
-                assert np.array_equal(out[s], oracle.eltwise_mult(fa, m[s], q))
-                ia = oracle.ntt_inverse(A2[s], q, psis[q])
-                assert np.array_equal(acc[s], oracle.eltwise_add(acc0[s], ia, q))
-            else:
+            fa = _fwd_canon(a[s], q)
+            assert np.array_equal(out[s], oracle.eltwise_mult(fa, m[s], q)), (p, l)
+            ia = _inv_canon(A2[s], q)
+            assert np.array_equal(acc[s], oracle.eltwise_add(acc0[s], ia, q)), (p, l)
+            if N > 4096:
                 fa = oracle.ntt_forward_at(a[s], idx, q, psis[q])
                 assert np.array_equal(out[s][idx], oracle.eltwise_mult(fa, m[s][idx], q))
-                ia = oracle.ntt_inverse_at(A2[s], idx, q, psis[q])
-                assert np.array_equal(acc[s][idx], oracle.eltwise_add(acc0[s][idx], ia, q))
     # in place: result == multiplier
     nt.ntt_forward_mul_rns(dm, to_dev(a), dm, N, moduli, B, 4, ws)
     assert np.array_equal(from_dev(dm), out)
@@ -586,10 +600,9 @@ def test_poly_mul_acc_rns(nt, logN, L, B):
     for p in range(B):
         for l, q in enumerate(moduli):
             s = slice((p * L + l) * N, (p * L + l + 1) * N)
-            if N <= 1024:
-                ab = oracle.negacyclic_mul(a[s], b[s], q)
-                assert np.array_equal(acc[s], oracle.eltwise_add(oracle.eltwise_add(acc0[s], ab, q), ab, q))
-            else:
+            ab = _prod_ref(a[s], b[s], q)
+            assert np.array_equal(acc[s], oracle.eltwise_add(oracle.eltwise_add(acc0[s], ab, q), ab, q)), (p, l)
+            if N > 1024:
                 ab = oracle.negacyclic_mul_at(a[s], b[s], idx, q)
                 ref = oracle.eltwise_add(oracle.eltwise_add(acc0[s][idx], ab, q), ab, q)
                 assert np.array_equal(acc[s][idx], ref)
@@ -620,8 +633,9 @@ def _check_batch_outputs(nt, tasks, host):
         full = N <= 2048
         idx = None if full else _sample_idx(N, 90 + logN, 12)
         if op == nt.BATCH_PRODUCT:
-            ref = oracle.negacyclic_mul(a, b, q) if full else oracle.negacyclic_mul_at(a, b, idx, q)
-            assert np.array_equal(got if full else got[idx], ref), ("product", logN)
+            assert np.array_equal(got, _prod_ref(a, b, q)), ("product", logN)
+            if not full:
+                assert np.array_equal(got[idx], oracle.negacyclic_mul_at(a, b, idx, q)), ("product", logN)
             continue
         fwd = op in (nt.BATCH_FWD, nt.BATCH_FWD_LAZY)
         bound = {nt.BATCH_FWD: 1, nt.BATCH_FWD_LAZY: 4, nt.BATCH_INV: 1, nt.BATCH_INV_LAZY: 2}[op]
@@ -631,6 +645,8 @@ def _check_batch_outputs(nt, tasks, host):
         else:
             ref = oracle.ntt_inverse(a, q, psi) if full else oracle.ntt_inverse_at(a, idx, q, psi)
         assert np.array_equal((got if full else got[idx]) % np.uint64(q), ref), (op, logN)
+        whole = _fwd_canon(a, q) if fwd else _inv_canon(a, q)
+        assert np.array_equal(got % np.uint64(q), whole), (op, logN)
         if fwd and bound == 4:         # lazy forward outputs equal the Harvey model
             assert np.array_equal(got, oracle.harvey_forward(a, q, psi, 4)), logN
 
@@ -738,10 +754,11 @@ def test_batch_rejects_bad_items(nt):
 def test_bench_step_full_size(nt):
     """The benchmark's step at its full size and launch configuration: 512 polynomials x 8
     limbs of the 50-bit primes at N = 2^14, forward(a) 1 -> 4 in one launch, then the fused
-    on-chip product accumulating into acc in one launch.  Checked three ways: sampled outputs
-    against the oracle's negacyclic product (Section 2), the whole arrays against the same
-    step run with the paper's butterflies (ntt_set_wide_range(0)), and every forward output
-    inside [0, 4q)."""
+    on-chip product accumulating into acc in one launch.  Checked four ways: every output of
+    every limb against the oracle (its product through the transforms, pinned on the CPU to
+    the schoolbook product), sampled outputs against the schoolbook definition of Section 2,
+    the whole arrays against the same step run with the paper's butterflies
+    (ntt_set_wide_range(0)), and every forward output inside [0, 4q)."""
     import torch
     N = PRIMES["rns_16384"]["N"]
     moduli = PRIMES["rns_16384"]["moduli"]
@@ -767,6 +784,10 @@ def test_bench_step_full_size(nt):
         nt.set_wide_range(True)
     assert torch.equal(results[True], results[False])
     got = from_dev(results[True])
+    # every output of every limb: the oracle's product through its transforms, plus acc
+    want = oracle.add_rns(acc0, oracle.product_rns(a, b, N, moduli), N, moduli)
+    bad = np.flatnonzero(got != want)
+    assert bad.size == 0, ("limbs differing from the oracle", np.unique(bad // N)[:16])
     idx = _sample_idx(N, 953, 6)
     for p, l in [(0, 0), (1, 7), (255, 3), (511, 5), (511, 7)]:
         q = moduli[l]
@@ -780,8 +801,8 @@ def test_batch_full_size_uneven(nt):
     polynomials, N uniform in {2^12..2^15}, 2..16 limbs of the 50-bit pool (2371 limb
     transforms), the grid autotuned, run as one persistent launch and from a captured
     graph.  Every limb's forward (1 -> 4) and inverse (1 -> 1) equals the per-call path's
-    words on the whole array (the paper's butterflies on both sides), and sampled limbs
-    equal the oracle's transforms at sampled indices."""
+    words and the oracle's (Harvey model for the lazy forward, canonical inverse) on the
+    whole array, and sampled limbs equal the direct definition at sampled indices."""
     import torch
     from synthetic import uniform_int
     pool = PRIMES["uneven"]["moduli"]
@@ -819,6 +840,21 @@ def test_batch_full_size_uneven(nt):
                 torch.cuda.synchronize()
                 assert torch.equal(dst, ref), (op, graph)
             got = from_dev(dst)
+            # every limb against the oracle: limbs grouped by (N, q), the forward's lazy words equal
+            # the Harvey model's (paper butterflies), the inverse's canonical values the definition's
+            groups = {}
+            for k, (n, q) in enumerate(limbs):
+                groups.setdefault((n, q), []).append(k)
+            for (n, q), ks in groups.items():
+                N = 1 << n
+                psi = oracle.min_root(N, q)
+                src_g = np.concatenate([host[offs[k]:offs[k] + N] for k in ks])
+                got_g = np.concatenate([got[offs[k]:offs[k] + N] for k in ks])
+                if fwd:
+                    want_g = oracle.harvey_forward_batch(src_g, N, q, psi, 4)
+                else:
+                    want_g = oracle.harvey_inverse_batch(src_g, N, q, psi, 1)
+                assert np.array_equal(got_g, want_g), (op, n, q)
             for k in samples:
                 n, q = limbs[k]
                 N, o = 1 << n, offs[k]

@@ -81,9 +81,18 @@ def _serve(nt, reqs, mode, stagger_us=0, **kw):
         srv.read(t, dst)
         outs.append(from_dev(dst))
         srv.release(t)
+    _settle(srv)
     st = srv.stats()
     srv.close()
     return outs, st
+
+
+def _settle(srv, timeout_s=10.0):
+    """Released ranges that were read return to the arena once the copies have run, which the
+    scheduler observes shortly after: wait for that."""
+    deadline = time.time() + timeout_s
+    while srv.stats()["arena_in_use"] and time.time() < deadline:
+        time.sleep(0.005)
 
 
 def test_server_mix_matches_alone_and_oracle(nt):
@@ -128,6 +137,7 @@ def test_server_backpressure_small_budget(nt):
         got = from_dev(dst)
         srv.release(t)
         assert np.array_equal(got, _alone(nt, r))
+    _settle(srv)
     st = srv.stats()
     assert st["completed"] == 12 and st["deferred"] > 0
     assert st["arena_peak"] <= 3 * fp and st["arena_in_use"] == 0
@@ -186,3 +196,36 @@ def test_server_rejects_malformed(nt):
     t0 = time.time()
     srv.close()                                                  # cancels the queued requests at once
     assert time.time() - t0 < 10
+
+
+def test_server_read_then_release_without_sync(nt):
+    """read() enqueues the copy on the caller's stream and release() follows at once, with no
+    synchronisation, while the next request waits for exactly that arena range (the budget
+    holds one result).  The caller's stream is kept busy first, so the copies run late; the
+    range must not be handed to the next request before its copy has run."""
+    import torch
+    reqs = [_request(unit_seed(350, k), 14, 4) for k in range(6)]
+    want = [_alone(nt, r) for r in reqs]
+    fp = (1 << 14) * 4 * 8
+    srv = nt.Server(hbm_budget=fp, streams=1)
+    side = torch.cuda.Stream()
+    busy = torch.zeros(1 << 27, dtype=torch.int64, device="cuda:0")
+    dsts = [empty_dev(r["N"] * 4) for r in reqs]
+    torch.cuda.synchronize()
+    tickets = [srv.submit(r["da"], r["db"], r["N"], r["mods"]) for r in reqs]
+    for t, dst in zip(tickets, dsts):
+        srv.wait(t, timeout_s=60)
+        with torch.cuda.stream(side):
+            for _ in range(8):
+                busy.add_(1)                 # delays the copy enqueued behind it
+        srv.read(t, dst, stream=side)
+        srv.release(t)                       # no synchronisation between read and release
+    srv.drain(timeout_s=60)
+    torch.cuda.synchronize()
+    for k, (dst, w) in enumerate(zip(dsts, want)):
+        assert np.array_equal(from_dev(dst), w), k
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["deferred"] > 0
+    _settle(srv)
+    assert srv.stats()["arena_in_use"] == 0
+    srv.close()
