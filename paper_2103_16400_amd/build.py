@@ -20,8 +20,7 @@ FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
     # no packed FP32 instructions anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # the hand-scheduled butterflies name fixed registers: a kernel whose register
-    # budget does not contain them must not build
+    # the butterflies' short assembly statements must assemble cleanly
     "-Werror=inline-asm",
 ]
 

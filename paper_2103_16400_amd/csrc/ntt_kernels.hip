@@ -39,12 +39,11 @@ namespace nttamd {
 
 // LASTPASS: this pass produces the transform's output (output mode MODE and,
 // for the inverse, the fused N^{-1} stage); PTOP: highest stage bit read from
-// the transposed sub-tables in the low pass (-1: none); HAND: hand-scheduled
-// butterflies (which need a 128-VGPR budget) or the plain C++ ones.
+// the transposed sub-tables in the low pass (-1: none); HAND: false for the
+// 64-VGPR schedule (twice the waves per SIMD).
 template <bool FWD, int LOGT, int LOGR, int LOGC, int LOGH, int MINW, int MODE, bool LASTPASS, int PTOP,
           bool HAND = true>
 __global__ void __launch_bounds__((1 << (LOGT + LOGH + LOGC)) >> LOGR, MINW) ntt_tile_kernel(const PassArgs a) {
-  static_assert(!HAND || MINW <= 4, "the butterflies use v122..v127: keep a budget of at least 128 VGPRs");
   using K = TileNtt<FWD, LOGT, LOGR, LOGC, LOGH, HAND>;
   __shared__ u64 lds[K::LDSW];
   const u32 item = a.item0 + blockIdx.y;
@@ -65,10 +64,9 @@ typedef void (*PassKernel)(const PassArgs);
 // tile, which hides more latency when the batch is small, at the price of more
 // LDS rounds.  The low pass reads the plan's transposed sub-tables only with
 // 2^kMpLogrLo coefficients per thread (the layout they are built for);
-// otherwise it reads the natural table.  The last variant uses the plain C++
-// butterflies, which need no fixed registers: with 4 coefficients per thread
-// it fits 64 VGPRs, so twice as many waves share a CU (more latency hidden, at
-// about 30% more VALU per butterfly).
+// otherwise it reads the natural table.  The last variant holds 4 coefficients
+// per thread within 64 VGPRs, so twice as many waves share a CU (more latency
+// hidden, at the price of more LDS rounds).
 constexpr int kVariants = 6;
 struct VariantShape { int hi, lo; bool hand; };
 static constexpr VariantShape kVariantShape[kVariants] = {{4, 4, true}, {3, 4, true}, {2, 4, true},
@@ -82,7 +80,7 @@ template <bool FWD, int LOGN, int MODE, bool LAST, int LOGR0, bool HAND = true>
 static PassKernel pick_hi_r() {
   constexpr int LT = mp_logt_hi(LOGN);
   constexpr int LOGR = hi_logr_clamped(LT, LOGR0);
-  // hand-scheduled butterflies: at least 128 VGPRs (they use v122..v127); C++ ones: 64
+  // register budget: 64 VGPRs for the 64-VGPR schedule, else 128 (256 for the widest tiles)
   constexpr int MW = !HAND ? 8 : (LOGR >= 4 && LT >= 9 ? 2 : 4);
   return ntt_tile_kernel<FWD, LT, LOGR, 4, 0, MW, MODE, LAST, -1, HAND>;
 }

@@ -16,7 +16,6 @@ namespace nttamd {
 // TBSEL: twiddle pairs per prefetch block for this use (0: the rule below).
 template <bool FWD, int LOGN, int LOGR, bool SPLIT, bool HAND = true, bool WIDE = false, int TBSEL = 0>
 struct OnChip {
-  static_assert(!WIDE || HAND, "the wide-range butterflies exist only hand-scheduled");
   static constexpr int N = 1 << LOGN;
   static constexpr int R = 1 << LOGR;
   static constexpr int NT = N >> LOGR;
@@ -26,9 +25,9 @@ struct OnChip {
   // Twiddle pairs per prefetch block.  The next block's loads are issued before
   // the current block's butterflies, so in the short-stride stages (one
   // butterfly per twiddle) a block must hold enough butterflies to cover the
-  // latency of an L2 hit.  At 32 coefficients per thread the 128-register
-  // budget allows one pair with the paper's forward butterflies and three with
-  // the wide ones (measured fastest; four spill).
+  // latency of an L2 hit.  At 32 coefficients per thread, within 128 registers:
+  // one pair with the paper's forward butterflies and three with the wide ones
+  // (measured fastest; four spill).
   static constexpr int TB = TBSEL > 0 ? TBSEL : (HAND && FWD && LOGR >= 5 ? (WIDE ? 3 : 1) : 2);
   using G = Geo<FWD, LOGN, LOGR>;
   using W = typename std::conditional<SPLIT, u32, u64>::type;

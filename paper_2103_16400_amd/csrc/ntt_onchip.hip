@@ -32,7 +32,6 @@ namespace nttamd {
 // MINW: waves per SIMD the register allocation must allow (occupancy target).
 template <bool FWD, int LOGN, int LOGR, bool SPLIT, int MINW, int MODE, bool WIDE>
 __global__ void __launch_bounds__(1 << (LOGN - LOGR), MINW) ntt_onchip_kernel(const PassArgs a) {
-  static_assert(MINW <= 4, "the butterflies use v122..v127: keep a budget of at least 128 VGPRs");
   using K = OnChip<FWD, LOGN, LOGR, SPLIT, true, WIDE>;
   __shared__ typename K::W lds[K::LDSW];
   const u32 item = a.item0 + blockIdx.x;
@@ -45,7 +44,6 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR), MINW) ntt_onchip_kernel(co
 // result (MODE canonical) or accumulator (MODE accumulate; may equal mul).
 template <int LOGN, int LOGR, bool SPLIT, int MINW, int MODE, bool WIDE>
 __global__ void __launch_bounds__(1 << (LOGN - LOGR), MINW) ntt_onchip_product_kernel(const PassArgs a) {
-  static_assert(MINW <= 4, "the butterflies use v122..v127: keep a budget of at least 128 VGPRs");
   using K = OnChip<true, LOGN, LOGR, SPLIT, true, WIDE>;
   __shared__ typename K::W lds[K::LDSW];
   const u32 item = a.item0 + blockIdx.x;
