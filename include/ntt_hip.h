@@ -267,6 +267,24 @@ ntt_status ntt_forward_mul_rns(uint64_t* result, const uint64_t* operand, const 
 ntt_status ntt_inverse_acc_rns(uint64_t* acc, const uint64_t* operand, uint64_t N, const uint64_t* moduli,
                                uint64_t num_limbs, uint64_t num_polys, uint64_t input_mod_factor,
                                uint64_t* workspace, ntt_stream_t stream);
+/* poly_mul_rns without any allocation, for callers that cannot allocate
+ * device memory at call time (code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and launches as
+ * poly_mul_rns, except:
+ *   - the workspace of N > 2^14 is a library-owned 32 MiB device array per
+ *     GPU (held until the process ends): num_polys * num_limbs * N words must
+ *     fit in 2^22 (e.g. 32 limbs at N = 2^17), else NTT_EINVAL_COUNT before
+ *     anything is launched;
+ *   - no plan is built: every (N, q) pair must already be in the library's
+ *     plan cache (created by an earlier call with it, e.g. poly_mul_rns or
+ *     ntt_forward_rns), else NTT_ENOTFOUND;
+ *   - the validation mode does not check its operands.
+ * All calls on one GPU share that GPU's workspace, which keeps the last
+ * call's contents: calls that overlap in time on one GPU (different streams
+ * or host threads) race and must be ordered by the caller. */
+ntt_status poly_mul_rns_noalloc(uint64_t* result, const uint64_t* a, const uint64_t* b, uint64_t N,
+                                const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
+                                ntt_stream_t stream);
 ntt_status poly_mul_acc_rns(uint64_t* acc, const uint64_t* a, const uint64_t* b, uint64_t N,
                             const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
                             uint64_t* workspace, ntt_stream_t stream);

@@ -46,6 +46,7 @@ _SIGS = {
     "eltwise_mult_mod_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _U64, _P]),
     "eltwise_add_mod_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P]),
     "poly_mul_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P, _P]),
+    "poly_mul_rns_noalloc": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P]),
     "ntt_forward_mul_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _U64, _P, _P]),
     "ntt_inverse_acc_rns": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _P, _P]),
     "poly_mul_acc_rns": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P, _P]),
@@ -257,6 +258,13 @@ def poly_mul_rns(result, a, b, N, moduli, num_polys, workspace=None, stream=None
     m, L = _moduli(moduli)
     _check(_lib.poly_mul_rns(_ptr(result), _ptr(a), _ptr(b), N, m, L, num_polys, _ptr(workspace),
                              _stream(stream)), "poly_mul_rns")
+
+
+def poly_mul_rns_noalloc(result, a, b, N, moduli, num_polys, stream=None):
+    """poly_mul_rns with the library's static workspace and cached plans only (allocates nothing)."""
+    m, L = _moduli(moduli)
+    _check(_lib.poly_mul_rns_noalloc(_ptr(result), _ptr(a), _ptr(b), N, m, L, num_polys, _stream(stream)),
+           "poly_mul_rns_noalloc")
 
 
 def ntt_forward_mul_rns(result, operand, multiplier, N, moduli, num_polys, input_mod_factor=1, workspace=None,

@@ -1,5 +1,6 @@
 // extern "C" entry points: argument validation, plan lookup, launches.
 #include <hip/hip_runtime.h>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -425,6 +426,84 @@ ntt_status poly_mul_rns(uint64_t* result, const uint64_t* a, const uint64_t* b, 
   if (st) return st;
   // result <- InvNTT(result), canonical
   return ntt_rns(false, result, result, nullptr, nullptr, N, moduli, num_limbs, num_polys, 1, 1, stream);
+}
+
+}  // extern "C"
+
+// ---- poly_mul_rns without allocation -----------------------------------------
+// The workspace of N > 2^14 products (the first pass of forward(b)) lives in a
+// file-scope device array instead of a caller's buffer.  Its device address is
+// taken once per device (hipGetSymbolAddress with that device current) and
+// kept; the array's name is only a host-side stand-in for it.
+namespace nttamd {
+constexpr uint64_t kScratchWords = 4ull << 20;            // 32 MiB per GPU
+__device__ __align__(256) uint64_t scratch[kScratchWords];
+}  // namespace nttamd
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+uint64_t* g_scratch_dev[kScratchDevices];                 // device address of `scratch`, per device
+
+ntt_status scratch_address(uint64_t** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) return NTT_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(nttamd::scratch)) != hipSuccess || !p) return NTT_EDEVICE;
+    g_scratch_dev[dev] = static_cast<uint64_t*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return NTT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+ntt_status poly_mul_rns_noalloc(uint64_t* result, const uint64_t* a, const uint64_t* b, uint64_t N,
+                                const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
+                                ntt_stream_t stream) {
+  if (!result || !a || !b || !moduli) return NTT_EINVAL_POINTER;
+  if (num_limbs == 0 || num_limbs > NTT_MAX_LIMBS || num_polys == 0) return NTT_EINVAL_COUNT;
+  ntt_status st = validate_degree(N);
+  if (st) return st;
+  if (num_polys > (1ull << 40) / (num_limbs * N)) return NTT_EINVAL_COUNT;
+  const size_t bytes = (size_t)(num_polys * num_limbs * N * sizeof(uint64_t));
+  if (overlaps(result, bytes, b, bytes)) return NTT_EALIAS;
+  st = check_alias(result, a, bytes);
+  if (st) return st;
+  const bool one_pass = is_one_pass(N);
+  if (!one_pass && bytes > kScratchWords * sizeof(uint64_t)) return NTT_EINVAL_COUNT;   // beyond the scratch
+  const ntt_plan* plans[NTT_MAX_LIMBS];
+  for (uint64_t l = 0; l < num_limbs; ++l) {
+    st = find_cached_plan(N, moduli[l], &plans[l]);
+    if (st) return st;
+  }
+  uint64_t* ws = nullptr;
+  if (!one_pass) {
+    st = scratch_address(&ws);
+    if (st) return st;
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  // the same launches as poly_mul_rns
+  NttLaunch l{result, a, nullptr, nullptr, plans, (uint32_t)num_limbs, num_polys, 1, 4, s};
+  st = launch_forward(l);                                  // result <- NTT(a), [0, 4q)
+  if (st) return st;
+  if (one_pass) {
+    NttLaunch p{result, b, result, nullptr, plans, (uint32_t)num_limbs, num_polys, 1, 1, s};
+    return launch_product(p, false);                       // result <- InvNTT(NTT(b) (.) result) on chip
+  }
+  l.in = b;
+  l.mul_into = result;
+  l.tmp = ws;
+  st = launch_forward(l);                                  // result <- NTT(b) (.) result, canonical
+  if (st) return st;
+  l.in = result;
+  l.mul_into = nullptr;
+  l.tmp = nullptr;
+  l.out_f = 1;
+  return launch_inverse(l);                                // result <- InvNTT(result)
 }
 
 ntt_status poly_mul_acc_rns(uint64_t* acc, const uint64_t* a, const uint64_t* b, uint64_t N,

@@ -90,6 +90,9 @@ ntt_status build_plan(ntt_plan** out, uint64_t N, uint64_t q, uint64_t psi);
 // Cached plan for (current device, N, q, smallest root); never freed before ntt_shutdown.
 ntt_status cached_plan(uint64_t N, uint64_t q, const ntt_plan** out);
 void clear_plan_cache();
+// The cached plan for (current device, N, q) without building one: NTT_ENOTFOUND
+// when no earlier call has created it.  Allocates nothing.
+ntt_status find_cached_plan(uint64_t N, uint64_t q, const ntt_plan** out);
 uint64_t barrett_factor(uint64_t q, uint32_t* qbits);
 
 // One limb task of the persistent batch kernel (ntt_batch.hip).

@@ -237,6 +237,19 @@ ntt_status cached_plan(uint64_t N, uint64_t q, const ntt_plan** out) {
   return NTT_OK;
 }
 
+ntt_status find_cached_plan(uint64_t N, uint64_t q, const ntt_plan** out) {
+  ntt_status st0 = validate_degree(N);
+  if (st0) return st0;
+  if (q < 3 || q >= (1ull << 62) || (q - 1) % (2 * N) != 0) return NTT_EINVAL_MODULUS;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return NTT_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto it = cache().find(CacheKey{dev, N, q});
+  if (it == cache().end()) return NTT_ENOTFOUND;
+  *out = it->second;
+  return NTT_OK;
+}
+
 void clear_plan_cache() {
   std::lock_guard<std::mutex> lk(g_cache_mu);
   for (auto& kv : cache()) {
