@@ -131,7 +131,7 @@ def cpu_baseline(N, moduli, psis, budget_s=12.0):
                       "definition, %d threads, %.1f s" % (done, N, min(done, len(moduli)), threads, el)}
 
 
-def time_large_ring(nt, torch, primes, reps=20):
+def time_large_ring(nt, torch, primes, reps=20, batches=(1, 2, 8)):
     """Forward and inverse NTT of 32-limb polynomials at N = 2^16 (60-bit primes), one
     launch sequence per batch of B polynomials, rotating over 16 distinct polynomials
     (256 MiB) so coefficients come from HBM rather than the 256 MB MALL.  Out of place, into
@@ -146,7 +146,7 @@ def time_large_ring(nt, torch, primes, reps=20):
     dst = torch.empty_like(data)
     stream = torch.cuda.current_stream()
     out = {}
-    for B in (1, 2, 8):
+    for B in batches:
         views = [(data[i * L * N:(i + B) * L * N], dst[i * L * N:(i + B) * L * N])
                  for i in range(0, pool - B + 1, B)]
         res = {}
@@ -444,6 +444,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=1.0, help="arrival window per rate")
     ap.add_argument("--serve-modes", default="batched,batched_persistent_only,fifo,fifo_per_limb",
                     help="comma-separated serving forms (batched_capK: batched with K wide launches per stream)")
+    ap.add_argument("--large-ring-only", type=int, default=0, metavar="B",
+                    help="only time the N = 2^16 x 32-limb forward and inverse at B polynomials per launch "
+                         "(for profiling the two-pass kernels)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 4 times (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -463,6 +466,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_dispatch": src.numel() * 8}), flush=True)
+        return
+
+    if args.large_ring_only:
+        print(json.dumps({"large_ring_n65536_l32": time_large_ring(nt, torch, load_primes(),
+                                                                   batches=(args.large_ring_only,))}), flush=True)
         return
 
     if args.serve_only:

@@ -46,11 +46,21 @@ template <bool FWD, int LOGT, int LOGR, int LOGC, int LOGH, int MINW, int MODE, 
 __global__ void __launch_bounds__((1 << (LOGT + LOGH + LOGC)) >> LOGR, MINW) ntt_tile_kernel(const PassArgs a) {
   using K = TileNtt<FWD, LOGT, LOGR, LOGC, LOGH, HAND>;
   __shared__ u64 lds[K::LDSW];
-  const u32 item = a.item0 + blockIdx.y;
+  // Workgroups are dispatched to the 8 XCDs in turn (linear id mod 8).  When the
+  // item count allows, every tile of an item goes to one XCD, in both passes, so
+  // the intermediate the first pass writes is read back through the same L2.
+  u32 yi = blockIdx.y, tile = blockIdx.x;
+  if ((gridDim.y & 7u) == 0) {
+    const u32 lin = blockIdx.x + blockIdx.y * gridDim.x;
+    const u32 k = lin >> 3;
+    yi = (lin & 7u) + 8u * (k / gridDim.x);
+    tile = k % gridDim.x;
+  }
+  const u32 item = a.item0 + yi;
   const u32 logN = a.logN;
   const PlanView pv = load_plan(a.plan[item % a.num_limbs], FWD, 1ull << logN);
   const u64 base = (u64)item << logN;
-  tile_body<FWD, LOGT, LOGR, LOGC, LOGH, MODE, LASTPASS, PTOP, HAND>(pv, logN, a.b0, blockIdx.x, a.in + base,
+  tile_body<FWD, LOGT, LOGR, LOGC, LOGH, MODE, LASTPASS, PTOP, HAND>(pv, logN, a.b0, tile, a.in + base,
                                                                     a.out + base, a.mul ? a.mul + base : nullptr, lds,
                                                                     true);
 }
