@@ -356,6 +356,14 @@ ntt_status poly_mul_acc_ntt_rns32(uint32_t* acc, const uint32_t* a_ntt, const ui
  *                             Section 4 product listing); tmp: N-word
  *                             workspace, required for N > 2^14, else ignored
  *   out may equal in; for products out must not overlap in2 or tmp.
+ *   input_mod_factor / output_mod_factor: the NTT class's factors per item
+ *   (Section 4); 0 selects the op's own (input 1 for forward and product, 2
+ *   for inverse; output as listed above).
+ *   Forward: input 1, 2 or 4, output 1 or 4; inverse: input 1 or 2, output
+ *   1 or 2; product: input 1, 2 or 4 (both factors), output 1.  A nonzero
+ *   output factor decides lazy or canonical output (the op then only gives
+ *   the direction); values outside these sets: NTT_EINVAL_FACTOR.  Operand
+ *   values must lie below input_mod_factor * q (checked in validation mode).
  * ntt_batch_create: a reusable batch context for up to `capacity` tasks (owns
  *   pinned and device descriptor buffers; not thread-safe: one context per
  *   host thread or external locking).
@@ -367,8 +375,9 @@ ntt_status poly_mul_acc_ntt_rns32(uint32_t* acc, const uint32_t* a_ntt, const ui
  * ntt_batch_run_graph: same work through a hipGraph (one per staging set)
  *   captured on first use:
  *   [descriptor copy, counter reset, persistent kernel]; the graph reads the
- *   task list and count from device memory, so it is replayed unchanged for
- *   every later batch of up to `capacity` tasks.
+ *   task list and count from device memory, so it is replayed for every later
+ *   batch of up to `capacity` tasks, its copy resized to the batch's own
+ *   descriptors before each replay.
  * ntt_batch_set_grid: number of persistent workgroups (0 = two per CU).
  */
 typedef struct ntt_batch ntt_batch;
@@ -385,7 +394,8 @@ typedef struct {
   uint64_t N;
   uint64_t q;
   uint32_t op;
-  uint32_t reserved;
+  uint16_t input_mod_factor;
+  uint16_t output_mod_factor;
 } ntt_batch_item;
 ntt_status ntt_batch_create(ntt_batch** batch, size_t capacity);
 ntt_status ntt_batch_destroy(ntt_batch* batch);

@@ -301,7 +301,8 @@ def set_variant(N, num_items, forward, variant):
 class BatchItem(ctypes.Structure):
     """ntt_batch_item of include/ntt_hip.h."""
     _fields_ = [("out", _P), ("in_", _P), ("in2", _P), ("tmp", _P), ("N", _U64), ("q", _U64),
-                ("op", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("op", ctypes.c_uint32), ("input_mod_factor", ctypes.c_uint16),
+                ("output_mod_factor", ctypes.c_uint16)]
 
 
 BATCH_FWD_LAZY, BATCH_FWD, BATCH_INV_LAZY, BATCH_INV, BATCH_PRODUCT = 0, 1, 2, 3, 4
@@ -332,10 +333,15 @@ class Batch:
 
     @staticmethod
     def make_items(tasks):
-        """tasks: iterable of (op, out, in, in2, tmp, N, q) with torch tensors (or None)."""
+        """tasks: iterable of (op, out, in, in2, tmp, N, q[, input_mod_factor, output_mod_factor]) with
+        torch tensors (or None); the factors default to 0 (the op's own)."""
         tasks = list(tasks)
         arr = (BatchItem * max(1, len(tasks)))()
-        for k, (op, out, inp, in2, tmp, N, q) in enumerate(tasks):
+        for k, task in enumerate(tasks):
+            op, out, inp, in2, tmp, N, q = task[:7]
+            if len(task) > 7:
+                arr[k].input_mod_factor = task[7]
+                arr[k].output_mod_factor = task[8] if len(task) > 8 else 0
             arr[k].out = _ptr(out)
             arr[k].in_ = _ptr(inp)
             arr[k].in2 = _ptr(in2)

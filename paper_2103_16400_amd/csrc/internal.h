@@ -105,6 +105,11 @@ struct BatchTask {
   uint32_t logN, op;
 };
 enum : uint32_t { kBatchFwdLazy = 0, kBatchFwdCanon = 1, kBatchInvLazy = 2, kBatchInvCanon = 3, kBatchProduct = 4 };
+// Set in BatchTask::op when the task's on-chip code (N <= 2^14) takes the
+// wide-range butterflies (modulus below kWideModulusBound, switch on).
+constexpr uint32_t kBatchWide = 0x100u;
+constexpr uint32_t kBatchOpMask = 0xffu;
+uint32_t batch_wide_flag(uint32_t logN, uint64_t q);
 
 // Kernel launchers (ntt_kernels.hip / eltwise.hip).
 struct NttLaunch {

@@ -38,6 +38,7 @@ struct ntt_batch_stage {
   bool pending;
   hipGraph_t graph;
   hipGraphExec_t graph_exec;
+  hipGraphNode_t copy_node;        // the graph's descriptor copy, resized before each replay
 };
 struct ntt_batch {
   int device;
@@ -63,11 +64,11 @@ constexpr int kBatchLdsWords32 = (1 << 14) + (1 << 14) / 32;   // 2^14 split exc
 
 // ---- one task -----------------------------------------------------------------
 
-template <bool FWD, int LOGN, int MODE>
+template <bool FWD, int LOGN, int MODE, bool WIDE>
 __device__ __attribute__((noinline)) void task_onchip(const u64* plan, const u64* in, u64* out, const u64* mul, u32* lds,
                                             bool nt) {
   const PlanView pv = load_plan(plan, FWD, 1ull << LOGN);
-  onchip_body<FWD, LOGN, LOGN - 9, true, MODE, true>(pv, in, out, mul, lds, nt);
+  onchip_body<FWD, LOGN, LOGN - 9, true, MODE, true, WIDE>(pv, in, out, mul, lds, nt);
 }
 
 // Both passes of a two-pass transform by one workgroup (512 threads, tiles of
@@ -103,39 +104,64 @@ __device__ __attribute__((noinline)) void task_twopass(const u64* plan, const u6
 }
 
 // Second half of a product on chip: out = InvNTT(NTT(b) (.) out), canonical.
-template <int LOGN>
+template <int LOGN, bool WIDE>
 __device__ __attribute__((noinline)) void task_product_onchip(const u64* plan, const u64* b, u64* out, u32* lds) {
   const PlanView pf = load_plan(plan, true, 1ull << LOGN);
   const PlanView pi = load_plan(plan, false, 1ull << LOGN);
-  onchip_product_body<LOGN, LOGN - 9, true, kOutCanon, true>(pf, pi, b, out, out, lds, true);
+  onchip_product_body<LOGN, LOGN - 9, true, kOutCanon, true, WIDE>(pf, pi, b, out, out, lds, true);
 }
 
+template <bool WIDE>
 __device__ __forceinline__ void run_product_onchip(u32 logN, const u64* plan, const u64* b, u64* out, void* lds) {
   u32* l32 = reinterpret_cast<u32*>(lds);
   switch (logN) {
-    case 10: task_product_onchip<10>(plan, b, out, l32); break;
-    case 11: task_product_onchip<11>(plan, b, out, l32); break;
-    case 12: task_product_onchip<12>(plan, b, out, l32); break;
-    case 13: task_product_onchip<13>(plan, b, out, l32); break;
-    case 14: task_product_onchip<14>(plan, b, out, l32); break;
+    case 10: task_product_onchip<10, WIDE>(plan, b, out, l32); break;
+    case 11: task_product_onchip<11, WIDE>(plan, b, out, l32); break;
+    case 12: task_product_onchip<12, WIDE>(plan, b, out, l32); break;
+    case 13: task_product_onchip<13, WIDE>(plan, b, out, l32); break;
+    case 14: task_product_onchip<14, WIDE>(plan, b, out, l32); break;
     default: break;
   }
 }
 
-template <bool FWD, int MODE>
+// WIDE applies to the single-pass sizes only; two-pass tasks run the paper's butterflies.
+template <bool FWD, int MODE, bool WIDE>
 __device__ __forceinline__ void run_transform(u32 logN, const u64* plan, const u64* in, u64* mid, u64* out,
                                               const u64* mul, void* lds, bool nt) {
   u32* l32 = reinterpret_cast<u32*>(lds);
   u64* l64 = reinterpret_cast<u64*>(lds);
   switch (logN) {
-    case 10: task_onchip<FWD, 10, MODE>(plan, in, out, mul, l32, nt); break;
-    case 11: task_onchip<FWD, 11, MODE>(plan, in, out, mul, l32, nt); break;
-    case 12: task_onchip<FWD, 12, MODE>(plan, in, out, mul, l32, nt); break;
-    case 13: task_onchip<FWD, 13, MODE>(plan, in, out, mul, l32, nt); break;
-    case 14: task_onchip<FWD, 14, MODE>(plan, in, out, mul, l32, nt); break;
+    case 10: task_onchip<FWD, 10, MODE, WIDE>(plan, in, out, mul, l32, nt); break;
+    case 11: task_onchip<FWD, 11, MODE, WIDE>(plan, in, out, mul, l32, nt); break;
+    case 12: task_onchip<FWD, 12, MODE, WIDE>(plan, in, out, mul, l32, nt); break;
+    case 13: task_onchip<FWD, 13, MODE, WIDE>(plan, in, out, mul, l32, nt); break;
+    case 14: task_onchip<FWD, 14, MODE, WIDE>(plan, in, out, mul, l32, nt); break;
     case 15: task_twopass<FWD, 15, MODE>(plan, in, mid, out, mul, l64, nt); break;
     case 16: task_twopass<FWD, 16, MODE>(plan, in, mid, out, mul, l64, nt); break;
     case 17: task_twopass<FWD, 17, MODE>(plan, in, mid, out, mul, l64, nt); break;
+    default: break;
+  }
+}
+
+template <bool WIDE>
+__device__ __forceinline__ void run_task(const BatchTask& tk, void* lds) {
+  switch (tk.op & kBatchOpMask) {
+    case kBatchFwdLazy: run_transform<true, kOutLazy, WIDE>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true); break;
+    case kBatchFwdCanon: run_transform<true, kOutCanon, WIDE>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true); break;
+    case kBatchInvLazy: run_transform<false, kOutLazy, WIDE>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true); break;
+    case kBatchInvCanon: run_transform<false, kOutCanon, WIDE>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true); break;
+    case kBatchProduct:
+      // out <- NTT(a) lazy; out <- NTT(b) (.) out (first pass of NTT(b) in tmp); out <- InvNTT(out)
+      run_transform<true, kOutLazy, WIDE>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true);
+      __syncthreads();
+      if (tk.logN <= (u32)kMaxOnchipLog) {        // the rest on chip, in one step
+        run_product_onchip<WIDE>(tk.logN, tk.plan, tk.in2, tk.out, lds);
+        break;
+      }
+      run_transform<true, kOutMul, false>(tk.logN, tk.plan, tk.in2, tk.tmp, tk.out, tk.out, lds, true);
+      __syncthreads();
+      run_transform<false, kOutCanon, false>(tk.logN, tk.plan, tk.out, tk.out, tk.out, nullptr, lds, false);
+      break;
     default: break;
   }
 }
@@ -157,25 +183,8 @@ __global__ void __launch_bounds__(kBatchThreads, 4)
     __syncthreads();
     if (i >= n) break;                          // every wave of every workgroup reaches this exit
     const BatchTask tk = tasks[i];
-    switch (tk.op) {
-      case kBatchFwdLazy: run_transform<true, kOutLazy>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true); break;
-      case kBatchFwdCanon: run_transform<true, kOutCanon>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true); break;
-      case kBatchInvLazy: run_transform<false, kOutLazy>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true); break;
-      case kBatchInvCanon: run_transform<false, kOutCanon>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true); break;
-      case kBatchProduct:
-        // out <- NTT(a) lazy; out <- NTT(b) (.) out (first pass of NTT(b) in tmp); out <- InvNTT(out)
-        run_transform<true, kOutLazy>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true);
-        __syncthreads();
-        if (tk.logN <= (u32)kMaxOnchipLog) {        // the rest on chip, in one step
-          run_product_onchip(tk.logN, tk.plan, tk.in2, tk.out, lds);
-          break;
-        }
-        run_transform<true, kOutMul>(tk.logN, tk.plan, tk.in2, tk.tmp, tk.out, tk.out, lds, true);
-        __syncthreads();
-        run_transform<false, kOutCanon>(tk.logN, tk.plan, tk.out, tk.out, tk.out, nullptr, lds, false);
-        break;
-      default: break;
-    }
+    if (tk.op & kBatchWide) run_task<true>(tk, lds);
+    else run_task<false>(tk, lds);
     __syncthreads();
   }
 }
@@ -184,7 +193,39 @@ __global__ void __launch_bounds__(kBatchThreads, 4)
 
 static uint64_t task_cost(uint32_t logN, uint32_t op) {
   const uint64_t n = 1ull << logN;
-  return n * logN * (op == kBatchProduct ? 3 : 1);
+  return n * logN * ((op & kBatchOpMask) == kBatchProduct ? 3 : 1);
+}
+
+uint32_t batch_wide_flag(uint32_t logN, uint64_t q) {
+  return (wide_range_enabled() && logN <= (uint32_t)kMaxOnchipLog && q < kWideModulusBound) ? kBatchWide : 0u;
+}
+
+// The task's operation from the item's op and modulus factors (0 = the op's own).
+static uint32_t default_in_f(uint32_t op) { return (op == kBatchInvLazy || op == kBatchInvCanon) ? 2u : 1u; }
+
+static ntt_status item_op(const ntt_batch_item& it, uint32_t* op, uint32_t* in_f) {
+  const uint32_t fi = it.input_mod_factor ? it.input_mod_factor : default_in_f(it.op);
+  const uint32_t fo = it.output_mod_factor;
+  switch (it.op) {
+    case kBatchFwdLazy:
+    case kBatchFwdCanon:
+      if (!(fi == 1 || fi == 2 || fi == 4) || !(fo == 0 || fo == 1 || fo == 4)) return NTT_EINVAL_FACTOR;
+      *op = fo == 0 ? it.op : (fo == 1 ? kBatchFwdCanon : kBatchFwdLazy);
+      break;
+    case kBatchInvLazy:
+    case kBatchInvCanon:
+      if (!(fi == 1 || fi == 2) || !(fo == 0 || fo == 1 || fo == 2)) return NTT_EINVAL_FACTOR;
+      *op = fo == 0 ? it.op : (fo == 1 ? kBatchInvCanon : kBatchInvLazy);
+      break;
+    case kBatchProduct:
+      if (!(fi == 1 || fi == 2 || fi == 4) || !(fo == 0 || fo == 1)) return NTT_EINVAL_FACTOR;
+      *op = kBatchProduct;
+      break;
+    default:
+      return NTT_EINVAL_FACTOR;
+  }
+  *in_f = fi;
+  return NTT_OK;
 }
 
 static ntt_status wait_staging(ntt_batch* b) {
@@ -208,7 +249,9 @@ ntt_status batch_prepare(ntt_batch* b, const ntt_batch_item* items, size_t count
     if (it.N < 1024) return NTT_EINVAL_DEGREE;
     int logN = 0;
     while ((1ull << logN) < it.N) ++logN;
-    if (it.op > kBatchProduct) return NTT_EINVAL_FACTOR;
+    uint32_t op = 0, in_f = 1;
+    st = item_op(it, &op, &in_f);
+    if (st) return st;
     if (it.op == kBatchProduct && !it.in2) return NTT_EINVAL_POINTER;
     if (it.op == kBatchProduct && logN > kMaxOnchipLog && !it.tmp) return NTT_EINVAL_POINTER;
     const size_t bytes = (size_t)it.N * sizeof(uint64_t);
@@ -239,13 +282,15 @@ ntt_status batch_prepare(ntt_batch* b, const ntt_batch_item* items, size_t count
       if (st) return st;
     }
     BatchTask& t = staged_tasks(b)[k];
+    uint32_t op = 0, in_f = 1;
+    (void)item_op(it, &op, &in_f);                 // validated above
     t.out = it.out;
     t.in = it.in;
     t.in2 = it.in2;
     t.tmp = it.tmp;
     t.plan = p->dev;
     t.logN = (uint32_t)p->logN;
-    t.op = it.op;
+    t.op = op | batch_wide_flag(t.logN, it.q);
   }
   *reinterpret_cast<uint32_t*>(cur_stage(b).host) = (uint32_t)count;
   *out_count = count;
@@ -306,7 +351,22 @@ static ntt_status batch_launch_staged(ntt_batch* b, size_t n, hipStream_t s, boo
         return NTT_EDEVICE;
       }
       sg.graph = g;
+      // find the descriptor copy, so each replay copies only its own batch's descriptors
+      size_t nn = 0;
+      sg.copy_node = nullptr;
+      if (hipGraphGetNodes(g, nullptr, &nn) == hipSuccess && nn > 0) {
+        std::vector<hipGraphNode_t> nodes(nn);
+        if (hipGraphGetNodes(g, nodes.data(), &nn) == hipSuccess) {
+          for (size_t i = 0; i < nn; ++i) {
+            hipGraphNodeType ty;
+            if (hipGraphNodeGetType(nodes[i], &ty) == hipSuccess && ty == hipGraphNodeTypeMemcpy) sg.copy_node = nodes[i];
+          }
+        }
+      }
     }
+    if (sg.copy_node && hipGraphExecMemcpyNodeSetParams1D(sg.graph_exec, sg.copy_node, sg.dev + kDevHead, sg.host,
+                                                          stage_bytes(n), hipMemcpyHostToDevice) != hipSuccess)
+      sg.copy_node = nullptr;                      // keep the captured full-capacity copy from here on
     if (hipGraphLaunch(sg.graph_exec, s) != hipSuccess) return NTT_EDEVICE;
   }
   if (hipEventRecord(sg.done, s) != hipSuccess) return NTT_EDEVICE;
@@ -445,9 +505,9 @@ static ntt_status check_items(const ntt_batch_item* items, size_t count, hipStre
   if (!validate_enabled()) return NTT_OK;
   for (size_t i = 0; i < count; ++i) {
     const ntt_batch_item& it = items[i];
-    const bool inv = it.op == NTT_BATCH_INV_LAZY || it.op == NTT_BATCH_INV;
-    ntt_status st = check_range(it.in, 64, it.N, &it.q, 1, 1, inv ? 2 : 1, stream);
-    if (!st && it.op == NTT_BATCH_PRODUCT) st = check_range(it.in2, 64, it.N, &it.q, 1, 1, 1, stream);
+    const uint64_t f = it.input_mod_factor ? it.input_mod_factor : default_in_f(it.op);
+    ntt_status st = check_range(it.in, 64, it.N, &it.q, 1, 1, f, stream);
+    if (!st && it.op == NTT_BATCH_PRODUCT) st = check_range(it.in2, 64, it.N, &it.q, 1, 1, f, stream);
     if (st) return st;
   }
   return NTT_OK;

@@ -409,7 +409,7 @@ bool launch(ntt_server* s) {
           t.tmp = tmp ? tmp + off : nullptr;
           t.plan = r->plans[l]->dev;
           t.logN = r->logN;
-          t.op = kBatchProduct;
+          t.op = kBatchProduct | batch_wide_flag(r->logN, r->moduli[l]);
           s->tasks.push_back(t);
         }
         r->state = NTT_REQ_RUNNING;

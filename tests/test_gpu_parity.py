@@ -647,7 +647,7 @@ def _check_batch_outputs(nt, tasks, host):
         assert np.array_equal((got if full else got[idx]) % np.uint64(q), ref), (op, logN)
         whole = _fwd_canon(a, q) if fwd else _inv_canon(a, q)
         assert np.array_equal(got % np.uint64(q), whole), (op, logN)
-        if fwd and bound == 4:         # lazy forward outputs equal the Harvey model
+        if fwd and bound == 4 and lazy_words_exact(nt, N, [q]):   # the paper's butterflies' lazy words
             assert np.array_equal(got, oracle.harvey_forward(a, q, psi, 4)), logN
 
 
@@ -662,28 +662,75 @@ def test_batch_uneven_mixed_ops(nt):
             k += 1
     tasks, host = _batch_case(nt, 100, specs)
     batch = nt.Batch(64)
-    batch.run(tasks)
-    _check_batch_outputs(nt, tasks, host)
-    # the same tasks through the per-call entry points give the same words (the batch
-    # kernel runs the paper's butterflies: compare with the per-call path doing the same)
-    nt.set_wide_range(False)
+    # with the wide-range butterflies (on-chip tasks whose modulus is below 2^58) and with the
+    # paper's everywhere: the oracle's results, and the per-call path's words under the same switch
     try:
-        for (op, out, da, db, tmp, N, q) in tasks[:10]:
-            ref = empty_dev(N)
-            if op == nt.BATCH_FWD_LAZY:
-                nt.ntt_forward(ref, da, N, q, 1, 4)
-            elif op == nt.BATCH_FWD:
-                nt.ntt_forward(ref, da, N, q, 1, 1)
-            elif op == nt.BATCH_INV_LAZY:
-                nt.ntt_inverse(ref, da, N, q, 1, 2)
-            elif op == nt.BATCH_INV:
-                nt.ntt_inverse(ref, da, N, q, 1, 1)
-            else:
-                continue
-            if op != nt.BATCH_INV_LAZY:      # lazy inverse representatives may differ between schedules
-                assert np.array_equal(from_dev(ref), from_dev(out)), (op, N)
+        for wide in (True, False):
+            nt.set_wide_range(wide)
+            for t in tasks:
+                t[1].zero_()
+            batch.run(tasks)
+            _check_batch_outputs(nt, tasks, host)
+            for (op, out, da, db, tmp, N, q) in tasks:
+                ref = empty_dev(N)
+                if op == nt.BATCH_FWD_LAZY:
+                    nt.ntt_forward(ref, da, N, q, 1, 4)
+                elif op == nt.BATCH_FWD:
+                    nt.ntt_forward(ref, da, N, q, 1, 1)
+                elif op == nt.BATCH_INV:
+                    nt.ntt_inverse(ref, da, N, q, 1, 1)
+                elif op == nt.BATCH_PRODUCT:
+                    nt.poly_mul_rns(ref, da, db, N, [q], 1, empty_dev(N))
+                else:
+                    continue                 # lazy inverse representatives may differ between schedules
+                assert np.array_equal(from_dev(ref), from_dev(out)), (wide, op, N)
     finally:
         nt.set_wide_range(True)
+    batch.close()
+
+
+def test_batch_item_factors(nt):
+    """Per-item input and output factors (the NTT class's input_mod_factor and
+    output_mod_factor, Section 4): a batched forward of lazy inputs in [0, 4q) with crafted
+    extremes, to lazy and canonical outputs; an inverse of inputs in [0, 2q); a product of
+    inputs in [0, 4q); each against the oracle on whole arrays.  Factors outside the
+    allowed sets are refused."""
+    serving = PRIMES["serving"]["moduli"]
+    specs = []
+    for k, logN in enumerate([10, 12, 14, 15, 16]):
+        q = serving[(5 * k) % len(serving)]
+        specs += [(nt.BATCH_FWD_LAZY, logN, q, 4, 4), (nt.BATCH_FWD_LAZY, logN, q, 4, 1),
+                  (nt.BATCH_FWD, logN, q, 2, 4), (nt.BATCH_INV, logN, q, 2, 2), (nt.BATCH_INV_LAZY, logN, q, 2, 1),
+                  (nt.BATCH_PRODUCT, logN, q, 4, 1)]
+    tasks, hosts = [], []
+    for k, (op, logN, q, fi, fo) in enumerate(specs):
+        N = 1 << logN
+        a = lazy_mod(unit_seed(130, k, 1), N, q, fi)
+        a[:4] = np.array([fi * q - 1, 0, q - 1, q], dtype=np.uint64)
+        b = lazy_mod(unit_seed(130, k, 2), N, q, fi) if op == nt.BATCH_PRODUCT else None
+        out = empty_dev(N)
+        tmp = empty_dev(N) if (op == nt.BATCH_PRODUCT and logN > 14) else None
+        tasks.append((op, out, to_dev(a), to_dev(b) if b is not None else None, tmp, N, q, fi, fo))
+        hosts.append((op, N, q, a, b, fo))
+    batch = nt.Batch(len(tasks))
+    batch.run(tasks)
+    for (op, out, *_), (_, N, q, a, b, fo) in zip(tasks, hosts):
+        got = from_dev(out)
+        qq = np.uint64(q)
+        if op == nt.BATCH_PRODUCT:
+            assert np.array_equal(got, _prod_ref(a % qq, b % qq, q)), (op, N)
+            continue
+        fwd = op in (nt.BATCH_FWD, nt.BATCH_FWD_LAZY)
+        assert np.all(got < np.uint64(fo * q)), (op, N, fo)
+        want = _fwd_canon(a, q) if fwd else _inv_canon(a, q)
+        assert np.array_equal(got % qq, want), (op, N, fo)
+    d = empty_dev(1024)
+    q = PRIMES["single_1024"]["moduli"][0]
+    for op, fi, fo in [(nt.BATCH_FWD, 3, 0), (nt.BATCH_FWD, 1, 2), (nt.BATCH_INV, 4, 0), (nt.BATCH_INV, 1, 4),
+                       (nt.BATCH_PRODUCT, 1, 4), (nt.BATCH_PRODUCT, 8, 0)]:
+        with pytest.raises(nt.NttError) as e:
+            batch.run([(op, d, d, d, None, 1024, q, fi, fo)])
+        assert e.value.status == nt.NTT_EINVAL_FACTOR, (op, fi, fo)
     batch.close()
 
 
@@ -823,50 +870,53 @@ def test_batch_full_size_uneven(nt):
     batch = nt.Batch(len(limbs))
     samples = [0, 1, len(limbs) // 2, len(limbs) - 1]
     try:
-        nt.set_wide_range(False)      # the batch kernel runs the paper's butterflies; so does the reference
-        for op, fwd in ((nt.BATCH_FWD_LAZY, True), (nt.BATCH_INV, False)):
-            items, cnt = nt.Batch.make_items([(op, dst[o:o + (1 << n)], src[o:o + (1 << n)], None, None, 1 << n, q)
-                                              for o, (n, q) in zip(offs, limbs)])
-            batch.autotune(items, cnt)
-            for graph in (False, True):
-                dst.zero_()
-                batch.run(items, cnt, graph=graph)
-                for o, (n, q) in zip(offs, limbs):
+        for wide in (False, True):
+            nt.set_wide_range(wide)       # the batch kernel and the per-call reference take the same butterflies
+            for op, fwd in ((nt.BATCH_FWD_LAZY, True), (nt.BATCH_INV, False)):
+                items, cnt = nt.Batch.make_items([(op, dst[o:o + (1 << n)], src[o:o + (1 << n)], None, None, 1 << n, q)
+                                                  for o, (n, q) in zip(offs, limbs)])
+                batch.autotune(items, cnt)
+                for graph in (False, True):
+                    dst.zero_()
+                    batch.run(items, cnt, graph=graph)
+                    for o, (n, q) in zip(offs, limbs):
+                        N = 1 << n
+                        if fwd:
+                            nt.ntt_forward(ref[o:o + N], src[o:o + N], N, q, 1, 4)
+                        else:
+                            nt.ntt_inverse(ref[o:o + N], src[o:o + N], N, q, 1, 1)
+                    torch.cuda.synchronize()
+                    assert torch.equal(dst, ref), (wide, op, graph)
+                got = from_dev(dst)
+                # every limb against the oracle: limbs grouped by (N, q), the forward's lazy words equal
+                # the Harvey model's (paper butterflies), the inverse's canonical values the definition's
+                groups = {}
+                for k, (n, q) in enumerate(limbs):
+                    groups.setdefault((n, q), []).append(k)
+                for (n, q), ks in groups.items():
                     N = 1 << n
-                    if fwd:
-                        nt.ntt_forward(ref[o:o + N], src[o:o + N], N, q, 1, 4)
+                    psi = oracle.min_root(N, q)
+                    src_g = np.concatenate([host[offs[k]:offs[k] + N] for k in ks])
+                    got_g = np.concatenate([got[offs[k]:offs[k] + N] for k in ks])
+                    if fwd and lazy_words_exact(nt, N, [q]):
+                        assert np.array_equal(got_g, oracle.harvey_forward_batch(src_g, N, q, psi, 4)), (op, n, q)
+                    elif fwd:
+                        assert np.all(got_g < np.uint64(4 * q)), (op, n, q)
+                        assert np.array_equal(got_g % np.uint64(q), oracle.harvey_forward_batch(src_g, N, q, psi, 1)), (op, n, q)
                     else:
-                        nt.ntt_inverse(ref[o:o + N], src[o:o + N], N, q, 1, 1)
-                torch.cuda.synchronize()
-                assert torch.equal(dst, ref), (op, graph)
-            got = from_dev(dst)
-            # every limb against the oracle: limbs grouped by (N, q), the forward's lazy words equal
-            # the Harvey model's (paper butterflies), the inverse's canonical values the definition's
-            groups = {}
-            for k, (n, q) in enumerate(limbs):
-                groups.setdefault((n, q), []).append(k)
-            for (n, q), ks in groups.items():
-                N = 1 << n
-                psi = oracle.min_root(N, q)
-                src_g = np.concatenate([host[offs[k]:offs[k] + N] for k in ks])
-                got_g = np.concatenate([got[offs[k]:offs[k] + N] for k in ks])
-                if fwd:
-                    want_g = oracle.harvey_forward_batch(src_g, N, q, psi, 4)
-                else:
-                    want_g = oracle.harvey_inverse_batch(src_g, N, q, psi, 1)
-                assert np.array_equal(got_g, want_g), (op, n, q)
-            for k in samples:
-                n, q = limbs[k]
-                N, o = 1 << n, offs[k]
-                a = host[o:o + N]
-                idx = _sample_idx(N, 960 + k, 8)
-                psi = oracle.min_root(N, q)
-                want = oracle.ntt_forward_at(a, idx, q, psi) if fwd else oracle.ntt_inverse_at(a, idx, q, psi)
-                assert np.array_equal(got[o:o + N][idx] % np.uint64(q), want), (op, k)
-                if fwd:
-                    assert np.all(got[o:o + N] < np.uint64(4 * q))
-                else:
-                    assert np.all(got[o:o + N] < np.uint64(q))
+                        assert np.array_equal(got_g, oracle.harvey_inverse_batch(src_g, N, q, psi, 1)), (op, n, q)
+                for k in samples:
+                    n, q = limbs[k]
+                    N, o = 1 << n, offs[k]
+                    a = host[o:o + N]
+                    idx = _sample_idx(N, 960 + k, 8)
+                    psi = oracle.min_root(N, q)
+                    want = oracle.ntt_forward_at(a, idx, q, psi) if fwd else oracle.ntt_inverse_at(a, idx, q, psi)
+                    assert np.array_equal(got[o:o + N][idx] % np.uint64(q), want), (op, k)
+                    if fwd:
+                        assert np.all(got[o:o + N] < np.uint64(4 * q))
+                    else:
+                        assert np.all(got[o:o + N] < np.uint64(q))
     finally:
         nt.set_wide_range(True)
         batch.close()
