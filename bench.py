@@ -333,8 +333,9 @@ def time_serving(nt, torch, primes, rates=SERVE_RATES, max_requests=4000, second
 
 
 def time_small_primes(nt, torch, primes, key="small_16384", B=512, steps=100, warmup=30):
-    """The step of the headline (forward of a, then the fused on-chip product into acc) at
-    word size 2^32: N = 2^14 (or 2^15), 8 limbs of primes below 2^30, 4-byte coefficients."""
+    """The step of the headline (forward of a, then the fused product into acc) at word size
+    2^32: N = 2^14 or 2^15 (on chip) or 2^16 (two passes per transform), 8 limbs of primes
+    below 2^30, 4-byte coefficients."""
     p = primes[key]
     N, moduli = p["N"], p["moduli"]
     L = len(moduli)
@@ -343,6 +344,7 @@ def time_small_primes(nt, torch, primes, key="small_16384", B=512, steps=100, wa
     b = torch.from_numpy(gen_operand(12, N, moduli, B).astype(np.uint32).view(np.int32)).to(dev)
     c = torch.empty_like(a)
     acc = torch.zeros_like(a)
+    ws = torch.empty_like(a) if N > (1 << 15) else None
     stream = torch.cuda.current_stream()
     ev = []
 
@@ -353,7 +355,7 @@ def time_small_primes(nt, torch, primes, key="small_16384", B=512, steps=100, wa
         nt.ntt_forward_rns32(c, a, N, moduli, B, 1, 4, stream=stream)
         if record:
             es[1].record(stream)
-        nt.poly_mul_acc_ntt_rns32(acc, c, b, N, moduli, B, stream=stream)
+        nt.poly_mul_acc_ntt_rns32(acc, c, b, N, moduli, B, ws, stream=stream)
         if record:
             es[2].record(stream)
             ev.append(es)
@@ -583,6 +585,7 @@ def main():
         out["single_n1024"] = time_single_1024(nt, torch, load_primes())
         out["small_primes_n16384_l8"] = time_small_primes(nt, torch, load_primes())
         out["small_primes_n32768_l8"] = time_small_primes(nt, torch, load_primes(), "small_32768", B=256)
+        out["small_primes_n65536_l8"] = time_small_primes(nt, torch, load_primes(), "small_65536", B=128)
         out["uneven_batch_256polys"] = time_uneven_batch(nt, torch, load_primes())
         if not args.no_serve:
             out["serving"] = time_serving(nt, torch, load_primes(), max_requests=args.serve_requests,

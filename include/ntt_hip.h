@@ -303,7 +303,7 @@ ntt_status poly_mul_acc_ntt_rns(uint64_t* acc, const uint64_t* a_ntt, const uint
 /* ---- Small moduli: word size 2^32 ---------------------------------------
  * Algorithms 2-5 (Section 3) at machine word beta = 2^32 instead of 2^64, for
  * moduli q < 2^30 (so that the lazy range 4q fits a 32-bit word), prime,
- * q = 1 mod 2N, and N a power of two in [2, 2^15]: the analogue of the
+ * q = 1 mod 2N, and N a power of two in [2, 2^17]: the analogue of the
  * paper's size-specialised IFMA52 path (Algorithms 6 and 7, beta = 2^52 for
  * q < 2^50).  Coefficients are uint32_t, laid out like the 64-bit calls
  * ([num_polys][num_limbs][N], limb l under moduli[l]); every product is a
@@ -313,11 +313,13 @@ ntt_status poly_mul_acc_ntt_rns(uint64_t* acc, const uint64_t* a_ntt, const uint
  * in [0, f q), f in {1, 2, 4}, and returns [0, 4q) (output factor 4, the words
  * Algorithm 4 produces at beta = 2^32) or [0, q) (factor 1); the inverse takes
  * [0, f q), f in {1, 2}, and returns [0, 2q) or [0, q), with N^{-1} fused into
- * its last stage.  Each call is one launch of one workgroup per limb (N = 2^15
- * takes 132 KiB of LDS: one workgroup per CU).
+ * its last stage.  Up to N = 2^15 each call is one launch of one workgroup per
+ * limb (N = 2^15 takes 132 KiB of LDS: one workgroup per CU); N = 2^16 and
+ * 2^17 take two passes over HBM (the split N = N1 N2 of Section 2.2), like
+ * the 64-bit calls.
  *
  * Errors: NTT_EINVAL_MODULUS for a modulus of 2^30 or more (or one that is
- * not a valid NTT prime for N), NTT_EINVAL_DEGREE for N above 2^15,
+ * not a valid NTT prime for N), NTT_EINVAL_DEGREE for N above 2^17,
  * NTT_EINVAL_FACTOR, NTT_EINVAL_COUNT, NTT_EINVAL_POINTER, and NTT_EALIAS when
  * an output partially overlaps an input (exact in-place is allowed where the
  * 64-bit call allows it). */
@@ -328,17 +330,22 @@ ntt_status ntt_inverse_rns32(uint32_t* result, const uint32_t* operand, uint64_t
                              uint64_t num_limbs, uint64_t num_polys, uint64_t input_mod_factor,
                              uint64_t output_mod_factor, ntt_stream_t stream);
 /* result = a * b mod (X^N + 1, q_l) per limb, canonical (the product listing of
- * Section 4): forward(a) in one launch, then one launch that keeps each limb
- * on chip for forward(b), the Algorithm 8 multiply and the inverse.  a and b
- * in [0, q); result may equal a, not b. */
+ * Section 4): forward(a) in one launch, then, up to N = 2^15, one launch that
+ * keeps each limb on chip for forward(b), the Algorithm 8 multiply and the
+ * inverse; at N = 2^16 and 2^17 forward(b) fused with the multiply and the
+ * inverse take two passes each.  a and b in [0, q); result may equal a, not b.
+ * workspace: num_polys * num_limbs * N words for the first pass of forward(b)
+ * at N >= 2^16 (NTT_EINVAL_POINTER without it), ignored (may be NULL) below;
+ * it must not overlap a, b or result. */
 ntt_status poly_mul_rns32(uint32_t* result, const uint32_t* a, const uint32_t* b, uint64_t N, const uint64_t* moduli,
-                          uint64_t num_limbs, uint64_t num_polys, ntt_stream_t stream);
+                          uint64_t num_limbs, uint64_t num_polys, uint32_t* workspace, ntt_stream_t stream);
 /* acc += a * b with a given as its forward transform (a_ntt in [0, 4q), e.g.
  * ntt_forward_rns32 with output factor 4), b in [0, q), acc canonical: one
- * launch.  acc must not overlap a_ntt or b. */
+ * launch up to N = 2^15, four passes at 2^16 and 2^17 (workspace as for
+ * poly_mul_rns32).  acc must not overlap a_ntt or b. */
 ntt_status poly_mul_acc_ntt_rns32(uint32_t* acc, const uint32_t* a_ntt, const uint32_t* b, uint64_t N,
                                   const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
-                                  ntt_stream_t stream);
+                                  uint32_t* workspace, ntt_stream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Batches of limb tasks with uneven ring degrees in one persistent launch.

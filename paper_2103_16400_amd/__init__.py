@@ -67,8 +67,8 @@ _SIGS = {
     "ntt_get_wide_range": (ctypes.c_int, []),
     "ntt_forward_rns32": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _U64, _P]),
     "ntt_inverse_rns32": (_ST, [_P, _P, _U64, _P, _U64, _U64, _U64, _U64, _P]),
-    "poly_mul_rns32": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P]),
-    "poly_mul_acc_ntt_rns32": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P]),
+    "poly_mul_rns32": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P, _P]),
+    "poly_mul_acc_ntt_rns32": (_ST, [_P, _P, _P, _U64, _P, _U64, _U64, _P, _P]),
     "eltwise_fma_mod_rns": (_ST, [_P, _P, _P, _P, _U64, _P, _U64, _U64, _U64, _P]),
     "eltwise_sub_mod": (_ST, [_P, _P, _P, _U64, _U64, _P]),
     "eltwise_negate_mod": (_ST, [_P, _P, _U64, _U64, _P]),
@@ -406,18 +406,18 @@ def ntt_inverse_rns32(result, operand, N, moduli, num_polys, input_mod_factor=1,
                                   output_mod_factor, _stream(stream)), "ntt_inverse_rns32")
 
 
-def poly_mul_rns32(result, a, b, N, moduli, num_polys, stream=None):
-    """result = a * b mod (X^N + 1, q_l) per limb at word size 2^32."""
+def poly_mul_rns32(result, a, b, N, moduli, num_polys, workspace=None, stream=None):
+    """result = a * b mod (X^N + 1, q_l) per limb at word size 2^32 (workspace needed at N >= 2^16)."""
     m, L = _moduli(moduli)
-    _check(_lib.poly_mul_rns32(_ptr32(result), _ptr32(a), _ptr32(b), N, m, L, num_polys, _stream(stream)),
-           "poly_mul_rns32")
+    _check(_lib.poly_mul_rns32(_ptr32(result), _ptr32(a), _ptr32(b), N, m, L, num_polys, _ptr32(workspace),
+                               _stream(stream)), "poly_mul_rns32")
 
 
-def poly_mul_acc_ntt_rns32(acc, a_ntt, b, N, moduli, num_polys, stream=None):
+def poly_mul_acc_ntt_rns32(acc, a_ntt, b, N, moduli, num_polys, workspace=None, stream=None):
     """acc += a * b at word size 2^32, with a given as its forward NTT (lazy outputs allowed)."""
     m, L = _moduli(moduli)
-    _check(_lib.poly_mul_acc_ntt_rns32(_ptr32(acc), _ptr32(a_ntt), _ptr32(b), N, m, L, num_polys, _stream(stream)),
-           "poly_mul_acc_ntt_rns32")
+    _check(_lib.poly_mul_acc_ntt_rns32(_ptr32(acc), _ptr32(a_ntt), _ptr32(b), N, m, L, num_polys, _ptr32(workspace),
+                                       _stream(stream)), "poly_mul_acc_ntt_rns32")
 
 
 def eltwise_fma_mod(result, arg1, arg2, arg3, n, modulus, input_mod_factor=1, stream=None):

@@ -83,9 +83,11 @@ ntt_status ntt_rns(bool fwd, uint64_t* result, const uint64_t* operand, const ui
   return fwd ? launch_forward(l) : launch_inverse(l);
 }
 
-// Word-size-2^32 path: moduli below 2^30 (4q < 2^32), N in [2, 2^15].
+// Word-size-2^32 path: moduli below 2^30 (4q < 2^32), N in [2, 2^17]; tmp: the
+// products' workspace at N >= 2^16.
 ntt_status small_call(uint32_t op, uint32_t* out, const uint32_t* in, const uint32_t* mul, uint64_t N,
-                      const uint64_t* moduli, uint64_t L, uint64_t B, uint64_t in_f, ntt_stream_t stream) {
+                      const uint64_t* moduli, uint64_t L, uint64_t B, uint64_t in_f, ntt_stream_t stream,
+                      uint32_t* tmp = nullptr) {
   if (!out || !in || !moduli) return NTT_EINVAL_POINTER;
   if (B == 0 || L == 0 || L > NTT_MAX_LIMBS) return NTT_EINVAL_COUNT;
   ntt_status st = validate_degree(N);
@@ -105,7 +107,7 @@ ntt_status small_call(uint32_t op, uint32_t* out, const uint32_t* in, const uint
     if (!st && op == kSmallProductAcc) st = check_range(out, 32, N, moduli, L, B, 1, (hipStream_t)stream);
     if (st) return st;
   }
-  Small32Launch l{out, in, mul, plans.data(), (uint32_t)L, B, logN, op, (hipStream_t)stream};
+  Small32Launch l{out, in, mul, tmp, plans.data(), (uint32_t)L, B, logN, op, (hipStream_t)stream};
   return launch_small(l);
 }
 
@@ -584,30 +586,46 @@ ntt_status ntt_inverse_rns32(uint32_t* result, const uint32_t* operand, uint64_t
                     moduli, num_limbs, num_polys, input_mod_factor, stream);
 }
 
+// The 32-bit products' workspace: required (and checked for overlap) at N >= 2^16.
+static ntt_status small_workspace(uint64_t N, const uint32_t* ws, size_t bytes, const void* x, const void* y,
+                                  const void* z) {
+  ntt_status st = validate_degree(N);                 // degree errors first
+  if (st) return st;
+  if (N <= (1ull << kMaxSmallOnePassLog)) return NTT_OK;
+  if (!ws) return NTT_EINVAL_POINTER;
+  if (overlaps(ws, bytes, x, bytes) || overlaps(ws, bytes, y, bytes) || overlaps(ws, bytes, z, bytes))
+    return NTT_EALIAS;
+  return NTT_OK;
+}
+
 ntt_status poly_mul_acc_ntt_rns32(uint32_t* acc, const uint32_t* a_ntt, const uint32_t* b, uint64_t N,
                                   const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
-                                  ntt_stream_t stream) {
+                                  uint32_t* workspace, ntt_stream_t stream) {
   if (!acc || !a_ntt || !b) return NTT_EINVAL_POINTER;
   if (num_limbs && num_polys && N && num_polys <= (1ull << 40) / (num_limbs * N)) {
     const size_t bytes = (size_t)(num_polys * num_limbs * N * sizeof(uint32_t));
     if (overlaps(acc, bytes, a_ntt, bytes) || overlaps(acc, bytes, b, bytes)) return NTT_EALIAS;
+    ntt_status st = small_workspace(N, workspace, bytes, acc, a_ntt, b);
+    if (st) return st;
   }
-  return small_call(kSmallProductAcc, acc, b, a_ntt, N, moduli, num_limbs, num_polys, 1, stream);
+  return small_call(kSmallProductAcc, acc, b, a_ntt, N, moduli, num_limbs, num_polys, 1, stream, workspace);
 }
 
 ntt_status poly_mul_rns32(uint32_t* result, const uint32_t* a, const uint32_t* b, uint64_t N, const uint64_t* moduli,
-                          uint64_t num_limbs, uint64_t num_polys, ntt_stream_t stream) {
+                          uint64_t num_limbs, uint64_t num_polys, uint32_t* workspace, ntt_stream_t stream) {
   if (!result || !a || !b) return NTT_EINVAL_POINTER;
   if (num_limbs && num_polys && N && num_polys <= (1ull << 40) / (num_limbs * N)) {
     const size_t bytes = (size_t)(num_polys * num_limbs * N * sizeof(uint32_t));
     if (overlaps(result, bytes, b, bytes)) return NTT_EALIAS;
     ntt_status st = check_alias(result, a, bytes);
     if (st) return st;
+    st = small_workspace(N, workspace, bytes, result, a, b);
+    if (st) return st;
   }
-  // result <- NTT(a) in [0, 4q); then on chip: result <- InvNTT(NTT(b) (.) result), canonical
+  // result <- NTT(a) in [0, 4q); then result <- InvNTT(NTT(b) (.) result), canonical
   ntt_status st = small_call(kSmallForwardLazy, result, a, nullptr, N, moduli, num_limbs, num_polys, 1, stream);
   if (st) return st;
-  return small_call(kSmallProduct, result, b, result, N, moduli, num_limbs, num_polys, 1, stream);
+  return small_call(kSmallProduct, result, b, result, N, moduli, num_limbs, num_polys, 1, stream, workspace);
 }
 
 ntt_status ntt_autotune(uint64_t N, const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,

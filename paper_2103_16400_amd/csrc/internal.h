@@ -156,8 +156,10 @@ ntt_status launch_eltwise_fma(const EltLaunch& l);                // b = addend 
 ntt_status batch_launch_tasks(ntt_batch* b, const BatchTask* tasks, size_t count, hipStream_t stream, bool graph);
 ntt_status launch_eltwise_add(const EltLaunch& l);
 
-// Word-size-2^32 transforms for moduli below 2^30 and N <= 2^15 (ntt_small.hip).
-constexpr int kMaxSmallLog = 15;
+// Word-size-2^32 transforms for moduli below 2^30 (ntt_small.hip): single pass
+// up to N = 2^15, two passes at 2^16 and 2^17.
+constexpr int kMaxSmallOnePassLog = 15;
+constexpr int kMaxSmallLog = 17;
 enum SmallOp : uint32_t {
   kSmallForwardLazy, kSmallForwardCanon, kSmallInverseLazy, kSmallInverseCanon, kSmallProduct, kSmallProductAcc
 };
@@ -165,6 +167,7 @@ struct Small32Launch {
   uint32_t* out;
   const uint32_t* in;
   const uint32_t* mul;          // products: the transformed multiplier (lazy, [0, 4q))
+  uint32_t* tmp;                // products at N >= 2^16: workspace of num_polys * num_limbs * N words
   const ntt_plan* const* plans; // num_limbs plans
   uint32_t num_limbs;
   uint64_t num_polys;

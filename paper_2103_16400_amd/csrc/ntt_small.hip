@@ -29,89 +29,10 @@
 
 #include "internal.h"
 #include "ntt_common.h"
+#include "small32.h"
+#include "tile32.h"
 
 namespace nttamd {
-
-struct View32 {
-  u32 q, q2, ninv, ninv_p, wn, wn_p, qbits;
-  u64 bk;
-  const ulonglong2* tw;
-  const ulonglong2* twp;
-};
-
-__device__ __forceinline__ View32 view32(const u64* plan, bool fwd, u64 N) {
-  const PlanView p = load_plan(plan, fwd, N);
-  View32 v;
-  v.q = (u32)p.q;
-  v.q2 = (u32)p.q2;
-  v.ninv = (u32)p.ninv;
-  v.ninv_p = (u32)(p.ninv_p >> 32);
-  v.wn = (u32)p.wn;
-  v.wn_p = (u32)(p.wn_p >> 32);
-  v.qbits = p.qbits;
-  v.bk = p.bk;
-  v.tw = p.tw;
-  v.twp = p.twp;
-  return v;
-}
-
-// Algorithm 4 at beta = 2^32 (inputs and outputs in [0, 4q)).  nt = -T mod 2^32
-// with T = W X1 - Q q in [0, 2q), so X0 + T = a - nt and X0 + 2q - T = a + 2q + nt.
-__device__ __forceinline__ void fwd_bfly32(u32& x0, u32& x1, u32 w, u32 wp, u32 q, u32 q2) {
-  const u32 a = min(x0, x0 - q2);
-  const u32 nt = __umulhi(wp, x1) * q - w * x1;
-  x0 = a - nt;
-  x1 = a + q2 + nt;
-}
-
-// Algorithm 5 at beta = 2^32 (inputs and outputs in [0, 2q)).
-__device__ __forceinline__ void inv_bfly32(u32& x0, u32& x1, u32 w, u32 wp, u32 q, u32 q2) {
-  const u32 s = x0 + x1;
-  const u32 d = x0 + q2 - x1;
-  x0 = min(s, s - q2);
-  x1 = w * d - __umulhi(wp, d) * q;
-}
-
-// Last Gentleman-Sande stage fused with the scaling by N^{-1}:
-// X0 <- N^{-1} (X0 + X1), X1 <- (W N^{-1}) (X0 - X1 + 2q), both in [0, 2q).
-__device__ __forceinline__ void inv_last32(u32& x0, u32& x1, const View32& v) {
-  const u32 s = x0 + x1;
-  const u32 d = x0 + v.q2 - x1;
-  x0 = v.ninv * s - __umulhi(v.ninv_p, s) * v.q;
-  x1 = v.wn * d - __umulhi(v.wn_p, d) * v.q;
-}
-
-// Algorithm 8 with input factor 4: x, y in [0, 4q) are reduced to [0, q), then
-// z = x y < q^2, c1 = z >> (Q - 1) < 2^(Q+1) <= 2^31, c3 = floor(c1 k / 2^64)
-// with k = floor(2^(63+Q) / q), and z - c3 q < 3q takes two conditional
-// subtractions.  c1 fits one word, so c1 k / 2^64 is one 32 x 32 high product
-// and one 32 x 32 -> 64 multiply-add.
-__device__ __forceinline__ u32 mulmod32_f4(u32 x, u32 y, const View32& v) {
-  x = min(x, x - v.q2);
-  x = min(x, x - v.q);
-  y = min(y, y - v.q2);
-  y = min(y, y - v.q);
-  const u64 z = (u64)x * y;
-  const u32 c1 = (u32)(z >> (v.qbits - 1));
-  const u64 t = (u64)c1 * (u32)(v.bk >> 32) + __umulhi(c1, (u32)v.bk);
-  const u32 c3 = (u32)(t >> 32);
-  u32 r = (u32)z - c3 * v.q;
-  r = min(r, r - v.q);
-  return min(r, r - v.q);
-}
-
-template <bool FWD, int MODE>
-__device__ __forceinline__ u32 finish32(u32 x, const u32* mul, u32 i, const View32& v) {
-  if (MODE == kOutCanon) {
-    if (FWD) x = min(x, x - v.q2);
-    return min(x, x - v.q);
-  }
-  if (!FWD && MODE == kOutAcc) {
-    const u32 r = mul[i] + min(x, x - v.q);     // acc < q plus a canonical value
-    return min(r, r - v.q);
-  }
-  return x;
-}
 
 template <bool FWD, int LOGN, int LOGR>
 struct OnChip32 {
@@ -367,8 +288,150 @@ static Kernel32 pick32_product(int logN) {
   }
 }
 
+// ---- two passes (N = 2^16, 2^17) -----------------------------------------------
+// The split N = N1 N2 of the 64-bit two-pass kernels: a high (strided) pass over
+// tiles of 16 adjacent columns with 8 coefficients per thread, and a low pass
+// over 4096 contiguous coefficients with 16 per thread, which reads the plan's
+// transposed sub-tables (laid out for that shape).  The forward runs high then
+// low, the inverse low then high (its fused N^{-1} stage is the high pass's
+// top bit).
+
+struct Tile32Args {
+  u32* out;
+  const u32* in;
+  const u32* mul;                          // kOutMul: multiplier; kOutAcc: accumulator (== out)
+  const u64* plan[kMaxPlansPerLaunch];     // item y uses plan[y % num_limbs]
+  u32 num_limbs;
+  u32 logN;
+  u32 b0;                                  // lowest index bit of this pass
+  u32 item0;
+};
+
+template <bool FWD, int LOGT, int LOGR, int LOGC, int LOGH, int MODE, bool LASTPASS, int PTOP>
+__global__ void __launch_bounds__((1 << (LOGT + LOGH + LOGC)) >> LOGR) ntt32_tile_kernel(const Tile32Args a) {
+  using K = Tile32<FWD, LOGT, LOGR, LOGC, LOGH>;
+  __shared__ u32 lds[K::LDSW];
+  // every tile of an item on one XCD (linear workgroup id mod 8) when the item count allows
+  u32 yi = blockIdx.y, tile = blockIdx.x;
+  if ((gridDim.y & 7u) == 0) {
+    const u32 lin = blockIdx.x + blockIdx.y * gridDim.x;
+    const u32 k = lin >> 3;
+    yi = (lin & 7u) + 8u * (k / gridDim.x);
+    tile = k % gridDim.x;
+  }
+  const u32 item = a.item0 + yi;
+  const View32 v = view32(a.plan[item % a.num_limbs], FWD, 1ull << a.logN);
+  const u64 base = (u64)item << a.logN;
+  tile32_body<FWD, LOGT, LOGR, LOGC, LOGH, MODE, LASTPASS, PTOP>(v, a.logN, a.b0, tile, a.in + base, a.out + base,
+                                                                a.mul ? a.mul + base : nullptr, lds);
+}
+
+typedef void (*Tile32Kernel)(const Tile32Args);
+
+template <int LOGN>
+struct TwoPass32 {
+  static constexpr int LT_LO = mp_logt_lo(LOGN), LT_HI = LOGN - LT_LO;
+  static constexpr int LH = 12 - LT_LO;               // low-pass tiles of 4096 coefficients
+  template <bool FWD, int MODE, bool LAST>
+  static Tile32Kernel hi() { return ntt32_tile_kernel<FWD, LT_HI, 3, 4, 0, MODE, LAST, -1>; }
+  template <bool FWD, int MODE, bool LAST>
+  static Tile32Kernel lo() { return ntt32_tile_kernel<FWD, LT_LO, kMpLogrLo, 0, LH, MODE, LAST, mp_perm_top(FWD, LOGN)>; }
+  static unsigned hi_threads() { return 1u << (LT_HI + 4 - 3); }
+  static unsigned lo_threads() { return 1u << (12 - kMpLogrLo); }
+  static unsigned hi_tiles() { return (1u << LT_LO) >> 4; }
+  static unsigned lo_tiles() { return 1u << (LOGN - 12); }
+};
+
+// One pass over `items` limbs (y of the grid), launched in chunks of at most 65535.
+static void pass32(Tile32Kernel k, unsigned tiles, unsigned threads, Tile32Args a, uint64_t items, hipStream_t s) {
+  const uint64_t kMaxY = 65535;
+  for (uint64_t it0 = 0; it0 < items; it0 += kMaxY) {
+    const uint64_t ny = (items - it0) < kMaxY ? (items - it0) : kMaxY;
+    a.item0 = (u32)it0;
+    hipLaunchKernelGGL(k, dim3(tiles, (unsigned)ny), dim3(threads), 0, s, a);
+  }
+}
+
+template <int LOGN>
+static ntt_status launch_small_twopass(const Small32Launch& l, Tile32Args a, uint64_t items) {
+  using T = TwoPass32<LOGN>;
+  const hipStream_t s = l.stream;
+  auto fwd_hi = [&](const u32* in, u32* out) {
+    Tile32Args h = a;
+    h.in = in;
+    h.out = out;
+    h.mul = nullptr;
+    h.b0 = T::LT_LO;
+    pass32(T::template hi<true, kOutLazy, false>(), T::hi_tiles(), T::hi_threads(), h, items, s);
+  };
+  auto fwd_lo = [&](Tile32Kernel k, const u32* in, u32* out, const u32* mul) {
+    Tile32Args h = a;
+    h.in = in;
+    h.out = out;
+    h.mul = mul;
+    h.b0 = 0;
+    pass32(k, T::lo_tiles(), T::lo_threads(), h, items, s);
+  };
+  auto inv_lo = [&](const u32* in, u32* out) {
+    Tile32Args h = a;
+    h.in = in;
+    h.out = out;
+    h.mul = nullptr;
+    h.b0 = 0;
+    pass32(T::template lo<false, kOutLazy, false>(), T::lo_tiles(), T::lo_threads(), h, items, s);
+  };
+  auto inv_hi = [&](Tile32Kernel k, const u32* in, u32* out, const u32* mul) {
+    Tile32Args h = a;
+    h.in = in;
+    h.out = out;
+    h.mul = mul;
+    h.b0 = T::LT_LO;
+    pass32(k, T::hi_tiles(), T::hi_threads(), h, items, s);
+  };
+  switch (l.op) {
+    case kSmallForwardLazy:
+    case kSmallForwardCanon:
+      fwd_hi(l.in, l.out);
+      fwd_lo(l.op == kSmallForwardLazy ? T::template lo<true, kOutLazy, true>() : T::template lo<true, kOutCanon, true>(),
+             l.out, l.out, nullptr);
+      break;
+    case kSmallInverseLazy:
+    case kSmallInverseCanon:
+      inv_lo(l.in, l.out);
+      inv_hi(l.op == kSmallInverseLazy ? T::template hi<false, kOutLazy, true>() : T::template hi<false, kOutCanon, true>(),
+             l.out, l.out, nullptr);
+      break;
+    case kSmallProduct:                            // out <- InvNTT(NTT(in) (.) mul), mul = NTT(a) (may be out)
+      if (!l.tmp) return NTT_EINVAL_POINTER;
+      fwd_hi(l.in, l.tmp);
+      fwd_lo(T::template lo<true, kOutMul, true>(), l.tmp, l.out, l.mul);
+      inv_lo(l.out, l.out);
+      inv_hi(T::template hi<false, kOutCanon, true>(), l.out, l.out, nullptr);
+      break;
+    case kSmallProductAcc:                         // out += InvNTT(NTT(in) (.) mul)
+      if (!l.tmp) return NTT_EINVAL_POINTER;
+      fwd_hi(l.in, l.tmp);
+      fwd_lo(T::template lo<true, kOutMul, true>(), l.tmp, l.tmp, l.mul);
+      inv_lo(l.tmp, l.tmp);
+      inv_hi(T::template hi<false, kOutAcc, true>(), l.tmp, l.out, l.out);
+      break;
+    default:
+      return NTT_EINVAL_FACTOR;
+  }
+  return hipGetLastError() == hipSuccess ? NTT_OK : NTT_EDEVICE;
+}
+
 ntt_status launch_small(const Small32Launch& l) {
   if (l.logN < 1 || l.logN > kMaxSmallLog) return NTT_EINVAL_DEGREE;
+  if (l.logN > kMaxSmallOnePassLog) {
+    if (l.num_limbs == 0 || l.num_limbs > (uint32_t)kMaxPlansPerLaunch) return NTT_EINVAL_COUNT;
+    Tile32Args a{};
+    for (uint32_t i = 0; i < l.num_limbs; ++i) a.plan[i] = l.plans[i]->dev;
+    a.num_limbs = l.num_limbs;
+    a.logN = (u32)l.logN;
+    const uint64_t items = l.num_polys * l.num_limbs;
+    return l.logN == 16 ? launch_small_twopass<16>(l, a, items) : launch_small_twopass<17>(l, a, items);
+  }
   if (l.num_limbs == 0 || l.num_limbs > (uint32_t)kMaxPlansPerLaunch) return NTT_EINVAL_COUNT;
   Kernel32 k = nullptr;
   switch (l.op) {

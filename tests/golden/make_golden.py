@@ -16,6 +16,7 @@ q prime, q < 2^62 and quotes timings on an unspecified 50-bit modulus):
   small_16384   8 largest primes < 2^30 that are 1 mod 2^15 (N = 2^14, 8 limbs,
                 for the word-size-2^32 path, which needs 4q < 2^32)
   small_32768   8 largest primes < 2^30 that are 1 mod 2^16 (N = 2^15, 8 limbs)
+  small_65536   8 largest primes < 2^30 that are 1 mod 2^17 (N = 2^16, 8 limbs, two passes)
 Run:  python tests/golden/make_golden.py
 """
 import json
@@ -49,6 +50,8 @@ def main():
     out["small_16384"] = {"N": 16384, "moduli": q6, "psi": [oracle.min_root(16384, q) for q in q6]}
     q7 = oracle.find_primes(30, 1 << 16, 8)
     out["small_32768"] = {"N": 32768, "moduli": q7, "psi": [oracle.min_root(32768, q) for q in q7]}
+    q8 = oracle.find_primes(30, 1 << 17, 8)
+    out["small_65536"] = {"N": 65536, "moduli": q8, "psi": [oracle.min_root(65536, q) for q in q8]}
     path = os.path.join(HERE, "primes.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)

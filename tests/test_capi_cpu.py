@@ -117,8 +117,9 @@ def test_server_config_validation_without_device(nt):
 
 
 def test_small_modulus_validation_without_device(nt):
-    """The word-size-2^32 calls reject moduli of 2^30 or more, N above 2^15, bad
-    factors, null pointers, empty batches and partial overlaps before any device work."""
+    """The word-size-2^32 calls reject moduli of 2^30 or more, N above 2^17, bad
+    factors, null pointers, empty batches, partial overlaps and a missing product
+    workspace at N >= 2^16 before any device work."""
     L = _raw(nt)
     fake = ctypes.c_void_p(0x1000000)
     other = ctypes.c_void_p(0x40000000)
@@ -129,7 +130,7 @@ def test_small_modulus_validation_without_device(nt):
     assert L.ntt_forward_rns32(fake, other, 1024, big, 1, 1, 1, 1, None) == nt.NTT_EINVAL_MODULUS
     assert L.ntt_forward_rns32(fake, other, 1024, q31, 1, 1, 1, 1, None) == nt.NTT_EINVAL_MODULUS
     assert L.ntt_inverse_rns32(fake, other, 1024, q31, 1, 1, 1, 1, None) == nt.NTT_EINVAL_MODULUS
-    assert L.ntt_forward_rns32(fake, other, 1 << 16, small, 1, 1, 1, 1, None) == nt.NTT_EINVAL_DEGREE
+    assert L.ntt_forward_rns32(fake, other, 1 << 18, small, 1, 1, 1, 1, None) == nt.NTT_EINVAL_DEGREE
     assert L.ntt_forward_rns32(fake, other, 1000, small, 1, 1, 1, 1, None) == nt.NTT_EINVAL_DEGREE
     assert L.ntt_forward_rns32(fake, other, 1024, small, 1, 1, 3, 1, None) == nt.NTT_EINVAL_FACTOR
     assert L.ntt_forward_rns32(fake, other, 1024, small, 1, 1, 1, 2, None) == nt.NTT_EINVAL_FACTOR
@@ -140,12 +141,16 @@ def test_small_modulus_validation_without_device(nt):
     assert L.ntt_forward_rns32(fake, other, 1024, small, 0, 1, 1, 1, None) == nt.NTT_EINVAL_COUNT
     assert L.ntt_forward_rns32(fake, other, 1024, small, 1, 0, 1, 1, None) == nt.NTT_EINVAL_COUNT
     assert L.ntt_forward_rns32(shifted, fake, 1024, small, 1, 1, 1, 1, None) == nt.NTT_EALIAS
-    assert L.poly_mul_rns32(fake, other, fake, 1024, small, 1, 1, None) == nt.NTT_EALIAS
-    assert L.poly_mul_rns32(fake, None, other, 1024, small, 1, 1, None) == nt.NTT_EINVAL_POINTER
-    assert L.poly_mul_acc_ntt_rns32(fake, fake, other, 1024, small, 1, 1, None) == nt.NTT_EALIAS
-    assert L.poly_mul_acc_ntt_rns32(fake, other, shifted, 1024, small, 1, 1, None) == nt.NTT_EALIAS
-    assert L.poly_mul_acc_ntt_rns32(fake, other, other, 1 << 16, small, 1, 1, None) == nt.NTT_EINVAL_DEGREE
-    assert L.poly_mul_acc_ntt_rns32(fake, other, other, 1024, big, 1, 1, None) == nt.NTT_EINVAL_MODULUS
+    assert L.poly_mul_rns32(fake, other, fake, 1024, small, 1, 1, None, None) == nt.NTT_EALIAS
+    assert L.poly_mul_rns32(fake, None, other, 1024, small, 1, 1, None, None) == nt.NTT_EINVAL_POINTER
+    assert L.poly_mul_acc_ntt_rns32(fake, fake, other, 1024, small, 1, 1, None, None) == nt.NTT_EALIAS
+    assert L.poly_mul_acc_ntt_rns32(fake, other, shifted, 1024, small, 1, 1, None, None) == nt.NTT_EALIAS
+    assert L.poly_mul_acc_ntt_rns32(fake, other, other, 1 << 18, small, 1, 1, None, None) == nt.NTT_EINVAL_DEGREE
+    assert L.poly_mul_acc_ntt_rns32(fake, other, other, 1024, big, 1, 1, None, None) == nt.NTT_EINVAL_MODULUS
+    third = ctypes.c_void_p(0x80000000)
+    assert L.poly_mul_rns32(fake, other, third, 1 << 16, small, 1, 1, None, None) == nt.NTT_EINVAL_POINTER
+    assert L.poly_mul_acc_ntt_rns32(fake, other, third, 1 << 17, small, 1, 1, None, None) == nt.NTT_EINVAL_POINTER
+    assert L.poly_mul_rns32(fake, other, third, 1 << 16, small, 1, 1, ctypes.c_void_p(0x1000000 + 8), None) == nt.NTT_EALIAS
 
 
 def test_validation_toggle_without_device(nt):

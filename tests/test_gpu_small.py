@@ -1,4 +1,5 @@
-"""GPU parity of the word-size-2^32 path (moduli below 2^30, N <= 2^15) through the C ABI.
+"""GPU parity of the word-size-2^32 path (moduli below 2^30, N <= 2^17; two passes at 2^16
+and 2^17) through the C ABI.
 
 Forward lazy outputs must be the exact words of Algorithms 2 + 4 at beta = 2^32
 (the oracle's word-size model, itself pinned to the direct definition);
@@ -74,7 +75,12 @@ def _idx(N, seed, k=24):
     return np.unique(np.concatenate([r, np.array([0, 1, N // 2, N - 1], dtype=np.uint64)]))
 
 
-LOGNS = [1, 2, 3, 4, 5, 8, 10, 11, 12, 13, 14, 15]
+LOGNS = [1, 2, 3, 4, 5, 8, 10, 11, 12, 13, 14, 15, 16, 17]
+
+
+def _ws(N, size):
+    """The products' workspace: needed from N = 2^16 (two passes)."""
+    return empty32(size) if N > (1 << 15) else None
 
 
 @pytest.mark.parametrize("logN", LOGNS)
@@ -121,6 +127,7 @@ def test_inverse32_definition_and_ranges(nt, logN):
                 psi = oracle.min_root(N, q)
                 assert np.all(gl[s] < np.uint64(2 * q)) and np.all(gc[s] < np.uint64(q))
                 assert np.array_equal(gl[s] % np.uint64(q), gc[s])
+                assert np.array_equal(gc[s], oracle.harvey_inverse(A[s], q, psi, 1)), (in_f, p, l, q)
                 if N <= 1024:
                     assert np.array_equal(gc[s], oracle.ntt_inverse(A[s], q, psi)), (in_f, p, l, q)
                 else:
@@ -141,7 +148,7 @@ def test_round_trip32_in_place(nt):
     assert np.array_equal(host32(d), a)
 
 
-@pytest.mark.parametrize("logN", [1, 3, 6, 10, 12, 13, 14, 15])
+@pytest.mark.parametrize("logN", [1, 3, 6, 10, 12, 13, 14, 15, 16, 17])
 def test_product32_against_schoolbook(nt, logN):
     N = 1 << logN
     moduli = _moduli(N, 3)
@@ -149,11 +156,11 @@ def test_product32_against_schoolbook(nt, logN):
     a = _inputs(230, N, moduli, B, 1)
     b = _inputs(231, N, moduli, B, 1)
     out = empty32(a.size)
-    nt.poly_mul_rns32(out, dev32(a), dev32(b), N, moduli, B)
+    nt.poly_mul_rns32(out, dev32(a), dev32(b), N, moduli, B, _ws(N, a.size))
     got = host32(out)
     # in place on a
     da = dev32(a)
-    nt.poly_mul_rns32(da, da, dev32(b), N, moduli, B)
+    nt.poly_mul_rns32(da, da, dev32(b), N, moduli, B, _ws(N, a.size))
     assert np.array_equal(host32(da), got)
     for p in range(B):
         for l, q in enumerate(moduli):
@@ -161,11 +168,14 @@ def test_product32_against_schoolbook(nt, logN):
             if N <= 1024:
                 assert np.array_equal(got[s], oracle.negacyclic_mul(a[s], b[s], q)), (p, l, q)
             else:
+                # every output: the oracle's product through its transforms (pinned to the schoolbook
+                # product on the CPU), and sampled outputs of the schoolbook definition itself
+                assert np.array_equal(got[s], oracle.product_batch(a[s], b[s], N, q)), (p, l, q)
                 idx = _idx(N, 232, 12)
                 assert np.array_equal(got[s][idx], oracle.negacyclic_mul_at(a[s], b[s], idx, q)), (p, l, q)
 
 
-@pytest.mark.parametrize("logN", [2, 10, 14, 15])
+@pytest.mark.parametrize("logN", [2, 10, 14, 15, 16, 17])
 def test_product32_acc_with_lazy_multipliers(nt, logN):
     """acc += InvNTT(NTT(b) (.) m) with m crafted in [0, 4q) up to 4q - 1 (the input
     factor 4 of the multiply), against the oracle's transforms and element-wise product."""
@@ -178,18 +188,18 @@ def test_product32_acc_with_lazy_multipliers(nt, logN):
     b = _inputs(241, N, moduli, 1, 1)
     acc0 = _inputs(242, N, moduli, 1, 1)
     dacc = dev32(acc0)
-    nt.poly_mul_acc_ntt_rns32(dacc, dev32(m), dev32(b), N, moduli, 1)
+    nt.poly_mul_acc_ntt_rns32(dacc, dev32(m), dev32(b), N, moduli, 1, _ws(N, m.size))
     got = host32(dacc)
-    idx = _idx(N, 243, 16)
     for l, q in enumerate(moduli):
         s = slice(l * N, (l + 1) * N)
         psi = oracle.min_root(N, q)
-        pm = oracle.eltwise_mult(oracle.ntt_forward(b[s], q, psi), m[s] % np.uint64(q), q)
         if N <= 1024:
+            pm = oracle.eltwise_mult(oracle.ntt_forward(b[s], q, psi), m[s] % np.uint64(q), q)
             assert np.array_equal(got[s], oracle.eltwise_add(acc0[s], oracle.ntt_inverse(pm, q, psi), q)), (l, q)
         else:
-            want = oracle.eltwise_add(acc0[s][idx], oracle.ntt_inverse_at(pm, idx, q, psi), q)
-            assert np.array_equal(got[s][idx], want), (l, q)
+            pm = oracle.eltwise_mult(oracle.harvey_forward(b[s], q, psi, 1), m[s] % np.uint64(q), q)
+            want = oracle.eltwise_add(acc0[s], oracle.harvey_inverse(pm, q, psi, 1), q)
+            assert np.array_equal(got[s], want), (l, q)
 
 
 def test_product32_pipeline_matches_64bit_path(nt):
@@ -208,33 +218,39 @@ def test_product32_pipeline_matches_64bit_path(nt):
     assert np.array_equal(host32(r32), from_dev(r64))
 
 
-def test_small_prime_step_full_size(nt):
-    """The benchmark's word-size-2^32 step at its full size: 512 polynomials x 8 limbs of the
-    largest primes below 2^30 at N = 2^14, forward(a) 1 -> 4 then the fused product into acc,
-    twice (so acc accumulates).  The canonical accumulator equals the 64-bit path's on the same
-    moduli word for word over the whole array, and sampled outputs equal the oracle's
-    negacyclic products (Section 2)."""
+@pytest.mark.parametrize("key,B", [("small_16384", 512), ("small_65536", 128)])
+def test_small_prime_step_full_size(nt, key, B):
+    """The benchmark's word-size-2^32 steps at their full size: B polynomials x 8 limbs of the
+    largest primes below 2^30 that suit N (N = 2^14 on chip, N = 2^16 in two passes), forward(a)
+    1 -> 4 then the fused product into acc, twice (so acc accumulates).  The canonical
+    accumulator equals the 64-bit path's on the same moduli word for word over the whole array,
+    and whole limbs equal the oracle's product (Section 2), with sampled outputs of the
+    schoolbook definition."""
     import torch
     from gpu_util import empty_dev, from_dev, to_dev
-    N = PRIMES["small_16384"]["N"]
-    moduli = SMALL
-    L, B = len(moduli), 512
+    N = PRIMES[key]["N"]
+    moduli = PRIMES[key]["moduli"]
+    L = len(moduli)
     a = _inputs(260, N, moduli, B, 1)
     b = _inputs(261, N, moduli, B, 1)
     da32, db32 = dev32(a), dev32(b)
     c32, acc32 = empty32(a.size), torch.zeros(a.size, dtype=torch.int32, device="cuda:0")
     da64, db64 = to_dev(a), to_dev(b)
     c64, acc64 = empty_dev(a.size), torch.zeros(a.size, dtype=torch.int64, device="cuda:0")
+    ws32 = _ws(N, a.size)
+    ws64 = empty_dev(2 * a.size) if N > (1 << 14) else None
     for _ in range(2):
         nt.ntt_forward_rns32(c32, da32, N, moduli, B, 1, 4)
-        nt.poly_mul_acc_ntt_rns32(acc32, c32, db32, N, moduli, B)
+        nt.poly_mul_acc_ntt_rns32(acc32, c32, db32, N, moduli, B, ws32)
         nt.ntt_forward_rns(c64, da64, N, moduli, B, 1, 4)
-        nt.poly_mul_acc_ntt_rns(acc64, c64, db64, N, moduli, B)
+        nt.poly_mul_acc_ntt_rns(acc64, c64, db64, N, moduli, B, ws64)
     got = host32(acc32)
     assert np.array_equal(got, from_dev(acc64))
     idx = _idx(N, 262, 6)
-    for p, l in [(0, 0), (200, 3), (511, 7)]:
+    for p, l in [(0, 0), (B // 2, 3), (B - 1, 7)]:
         q = moduli[l]
         s = slice((p * L + l) * N, (p * L + l + 1) * N)
+        whole = oracle.product_batch(a[s], b[s], N, q)
+        assert np.array_equal(got[s], oracle.eltwise_add(whole, whole, q)), (p, l)
         prod = oracle.negacyclic_mul_at(a[s], b[s], idx, q)
         assert np.array_equal(got[s][idx], oracle.eltwise_add(prod, prod, q)), (p, l)
