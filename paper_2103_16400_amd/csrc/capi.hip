@@ -628,6 +628,24 @@ ntt_status poly_mul_rns32(uint32_t* result, const uint32_t* a, const uint32_t* b
   return small_call(kSmallProduct, result, b, result, N, moduli, num_limbs, num_polys, 1, stream, workspace);
 }
 
+}  // extern "C"
+
+namespace {
+// Autotuner operands: every word a hash of its index, shifted below 2^(bits - 1),
+// so below every modulus of the launch (the smallest has `bits` bits): uniform
+// data within the declared input range, as a real workload's.
+__global__ void autotune_fill_kernel(uint64_t* buf, uint64_t words, uint32_t bits) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t z = i + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    buf[i] = (z ^ (z >> 31)) >> (65 - bits);
+  }
+}
+}  // namespace
+
+extern "C" {
+
 ntt_status ntt_autotune(uint64_t N, const uint64_t* moduli, uint64_t num_limbs, uint64_t num_polys,
                         ntt_stream_t stream, int* choice_fwd, int* choice_inv) {
   if (!moduli) return NTT_EINVAL_POINTER;
@@ -653,7 +671,15 @@ ntt_status ntt_autotune(uint64_t N, const uint64_t* moduli, uint64_t num_limbs, 
       if (rot <= 2) return NTT_ENOMEM;
       rot /= 2;
     }
-    if (hipMemsetAsync(buf, 0, rot * bytes, (hipStream_t)stream) != hipSuccess) { (void)hipFree(buf); return NTT_EDEVICE; }
+    uint32_t bits = 64;
+    for (const ntt_plan* p : plans) bits = p->host_header.qbits < bits ? (uint32_t)p->host_header.qbits : bits;
+    // refilled before each direction's trials: the inverse's trials need inputs below 2q
+    auto fill = [&]() {
+      hipLaunchKernelGGL(autotune_fill_kernel, dim3(1024), dim3(256), 0, (hipStream_t)stream, buf,
+                         (uint64_t)(rot * bytes / sizeof(uint64_t)), bits);
+    };
+    fill();
+    if (hipGetLastError() != hipSuccess) { (void)hipFree(buf); return NTT_EDEVICE; }
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
@@ -661,8 +687,8 @@ ntt_status ntt_autotune(uint64_t N, const uint64_t* moduli, uint64_t num_limbs, 
     const int nv = hi_variant_count();
     auto run = [&](int dir, int v, int r) {
       uint64_t* x = buf + (size_t)(r % rot) * (bytes / sizeof(uint64_t));
-      // zero-filled operands, transformed in place: every value stays within the
-      // input range declared here (forward inputs below 4q, inverse inputs below 2q)
+      // operands below q, transformed in place: every value stays within the input
+      // range declared here (forward inputs below 4q, inverse inputs below 2q)
       NttLaunch l{x, x, nullptr, nullptr, plans.data(), (uint32_t)num_limbs, num_polys, dir ? 4u : 2u,
                   dir ? 4u : 2u, (hipStream_t)stream};
       launch_variant(l, dir == 1, v);
@@ -670,10 +696,13 @@ ntt_status ntt_autotune(uint64_t N, const uint64_t* moduli, uint64_t num_limbs, 
     // the clocks rise over the first few milliseconds of work: warm up on every variant
     // first, then take each variant's best of two rounds, so the order of the trials
     // does not favour the later ones
-    for (int dir = 0; dir < 2; ++dir)
+    for (int dir = 0; dir < 2; ++dir) {
+      fill();
       for (int v = 0; v < nv; ++v)
         for (int w = 0; w < 5; ++w) run(dir, v, w);
+    }
     for (int dir = 0; dir < 2; ++dir) {
+      fill();
       std::vector<float> t(nv, 1e30f);
       for (int round = 0; round < 2; ++round) {
         for (int v = 0; v < nv; ++v) {

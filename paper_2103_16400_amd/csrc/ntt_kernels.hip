@@ -74,28 +74,43 @@ typedef void (*PassKernel)(const PassArgs);
 // tile, which hides more latency when the batch is small, at the price of more
 // LDS rounds.  The low pass reads the plan's transposed sub-tables only with
 // 2^kMpLogrLo coefficients per thread (the layout they are built for);
-// otherwise it reads the natural table.  The last variant holds 4 coefficients
-// per thread within 64 VGPRs, so twice as many waves share a CU (more latency
-// hidden, at the price of more LDS rounds).
-constexpr int kVariants = 6;
-struct VariantShape { int hi, lo; bool hand; };
-static constexpr VariantShape kVariantShape[kVariants] = {{4, 4, true}, {3, 4, true}, {2, 4, true},
-                                                          {3, 3, true}, {2, 3, true}, {2, 2, false}};
-// At most 1024 threads per workgroup: 2^(tile bits + 4 columns - log2 R).
-__host__ __device__ constexpr int hi_logr_clamped(int lt_hi, int logr) { return lt_hi + 4 - logr > 10 ? lt_hi - 6 : logr; }
-static int hi_logr(int logN, int variant) { return hi_logr_clamped(mp_logt_hi(logN), kVariantShape[variant].hi); }
+// otherwise it reads the natural table.  Variant 5 holds 4 coefficients per
+// thread within 64 VGPRs, so twice as many waves share a CU (more latency
+// hidden, at the price of more LDS rounds).  Variants 6 and 7 move the split
+// N = N1 N2 (Section 2.2) one index bit either way: the low pass covers one
+// bit fewer or one more than the default (reading the natural table), the
+// high pass the rest, with 8 columns per tile where its tile would otherwise
+// exceed 1024 threads of 8 coefficients.
+constexpr int kVariants = 8;
+struct VariantShape { int hi, lo; bool hand; int dlo; };
+static constexpr VariantShape kVariantShape[kVariants] = {
+    {4, 4, true, 0}, {3, 4, true, 0}, {2, 4, true, 0}, {3, 3, true, 0},
+    {2, 3, true, 0}, {2, 2, false, 0}, {3, 4, true, -1}, {3, 4, true, 1}};
+// Index bits of the low pass for a variant, and columns per high-pass tile.
+static int variant_lt_lo(int logN, int variant) { return mp_logt_lo(logN) + kVariantShape[variant].dlo; }
+__host__ __device__ constexpr int hi_logc(int lt_hi) { return lt_hi >= 10 ? 3 : 4; }
+// At most 1024 threads per workgroup: 2^(tile bits + column bits - log2 R).
+__host__ __device__ constexpr int hi_logr_clamped(int lt_hi, int logr) {
+  return lt_hi + hi_logc(lt_hi) - logr > 10 ? lt_hi + hi_logc(lt_hi) - 10 : logr;
+}
+static int hi_logr(int logN, int variant) {
+  return hi_logr_clamped(logN - variant_lt_lo(logN, variant), kVariantShape[variant].hi);
+}
 static int lo_logr(int variant) { return kVariantShape[variant].lo; }
 
-template <bool FWD, int LOGN, int MODE, bool LAST, int LOGR0, bool HAND = true>
+template <bool FWD, int LOGN, int MODE, bool LAST, int LOGR0, bool HAND = true, int LTLO = mp_logt_lo(LOGN)>
 static PassKernel pick_hi_r() {
-  constexpr int LT = mp_logt_hi(LOGN);
+  constexpr int LT = LOGN - LTLO;
+  constexpr int LC = hi_logc(LT);
   constexpr int LOGR = hi_logr_clamped(LT, LOGR0);
   // register budget: 64 VGPRs for the 64-VGPR schedule, else 128 (256 for the widest tiles)
   constexpr int MW = !HAND ? 8 : (LOGR >= 4 && LT >= 9 ? 2 : 4);
-  return ntt_tile_kernel<FWD, LT, LOGR, 4, 0, MW, MODE, LAST, -1, HAND>;
+  return ntt_tile_kernel<FWD, LT, LOGR, LC, 0, MW, MODE, LAST, -1, HAND>;
 }
 template <bool FWD, int LOGN, int MODE, bool LAST>
 static PassKernel pick_hi(int variant) {
+  if (kVariantShape[variant].dlo < 0) return pick_hi_r<FWD, LOGN, MODE, LAST, 3, true, mp_logt_lo(LOGN) - 1>();
+  if (kVariantShape[variant].dlo > 0) return pick_hi_r<FWD, LOGN, MODE, LAST, 3, true, mp_logt_lo(LOGN) + 1>();
   if (!kVariantShape[variant].hand) return pick_hi_r<FWD, LOGN, MODE, LAST, 2, false>();
   switch (kVariantShape[variant].hi) {
     case 4: return pick_hi_r<FWD, LOGN, MODE, LAST, 4>();
@@ -107,6 +122,8 @@ template <bool FWD, int LOGN, int MODE, bool LAST>
 static PassKernel pick_lo(int variant) {
   constexpr int LT = mp_logt_lo(LOGN);
   constexpr int LH = 12 - LT;                          // 4096-coefficient tiles
+  if (kVariantShape[variant].dlo < 0) return ntt_tile_kernel<FWD, LT - 1, kMpLogrLo, 0, LH + 1, 4, MODE, LAST, -1>;
+  if (kVariantShape[variant].dlo > 0) return ntt_tile_kernel<FWD, LT + 1, kMpLogrLo, 0, LH - 1, 4, MODE, LAST, -1>;
   if (lo_logr(variant) == kMpLogrLo) return ntt_tile_kernel<FWD, LT, kMpLogrLo, 0, LH, 4, MODE, LAST, mp_perm_top(FWD, LOGN)>;
   if (!kVariantShape[variant].hand) return ntt_tile_kernel<FWD, LT, 2, 0, LH, 8, MODE, LAST, -1, false>;
   return ntt_tile_kernel<FWD, LT, 3, 0, LH, 4, MODE, LAST, -1>;
@@ -138,14 +155,24 @@ static PassKernel pick_pass_n(int logN, bool fwd, bool hi, u32 flags, int varian
 // Number of passes the schedule for 2^logN uses (1 = the whole transform on chip).
 int pass_count(int logN) { return logN <= kMaxOnchipLog ? 1 : 2; }
 
-// Schedule variant per (direction, logN, batch size); set by the autotuner.
-static int g_hi_variant[2][NTT_MAX_LOG_DEGREE + 1][2];
+// Schedule variant per (device, direction, logN, batch size); set by the autotuner
+// on the device it ran on, read by every launch there (atomics: calls may come
+// from several host threads).
+constexpr int kVariantDevices = 64;
+static std::atomic<int> g_hi_variant[kVariantDevices][2][NTT_MAX_LOG_DEGREE + 1][2];
 static int batch_bucket(uint64_t items) { return items <= 64 ? 0 : 1; }
+static int variant_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kVariantDevices) dev = 0;
+  return dev;
+}
 
 void set_hi_variant(bool fwd, int logN, uint64_t items, int variant) {
-  g_hi_variant[fwd ? 1 : 0][logN][batch_bucket(items)] = variant;
+  g_hi_variant[variant_device()][fwd ? 1 : 0][logN][batch_bucket(items)].store(variant, std::memory_order_relaxed);
 }
-int get_hi_variant(bool fwd, int logN, uint64_t items) { return g_hi_variant[fwd ? 1 : 0][logN][batch_bucket(items)]; }
+int get_hi_variant(bool fwd, int logN, uint64_t items) {
+  return g_hi_variant[variant_device()][fwd ? 1 : 0][logN][batch_bucket(items)].load(std::memory_order_relaxed);
+}
 int hi_variant_count() { return kVariants; }
 
 static std::atomic<int> g_wide_range{1};
@@ -187,7 +214,8 @@ static ntt_status launch_passes(const NttLaunch& l, bool fwd, int force_variant)
   }
   if (logN > NTT_MAX_LOG_DEGREE) return NTT_EINVAL_DEGREE;
   const int variant = force_variant >= 0 ? force_variant : get_hi_variant(fwd, logN, items);
-  const int lt_lo = mp_logt_lo(logN), lt_hi = mp_logt_hi(logN);
+  if (variant < 0 || variant >= kVariants) return NTT_EINVAL_COUNT;
+  const int lt_lo = variant_lt_lo(logN, variant), lt_hi = logN - lt_lo;
   uint64_t* mid = l.tmp ? l.tmp : l.out;
   const uint64_t kMaxY = 65535;
   for (int step = 0; step < 2; ++step) {
@@ -202,9 +230,9 @@ static ntt_status launch_passes(const NttLaunch& l, bool fwd, int force_variant)
     uint64_t tiles;
     if (hi) {
       a.b0 = (u32)lt_lo;
-      const int logr = hi_logr(logN, variant);
-      nt = 1 << (lt_hi + 4 - logr);
-      tiles = ((1ull << lt_lo) >> 4) * (1ull << (logN - lt_lo - lt_hi));
+      const int logr = hi_logr(logN, variant), logc = hi_logc(lt_hi);
+      nt = 1 << (lt_hi + logc - logr);
+      tiles = (1ull << lt_lo) >> logc;
     } else {
       a.b0 = 0;
       nt = 1 << (12 - lo_logr(variant));
