@@ -46,10 +46,10 @@ HBM_PEAK_GBS = 8000.0
 # Valid only for the kernel sources they were taken with, identified by the SHA-256 of these files.
 COUNTERS_N16384 = {
     "sources": ["ntt_onchip.hip", "ntt_onchip.h", "ntt_common.h", "modarith.h", "internal.h", "ntt_kernels.hip"],
-    "sha256": "516e57be2cb3d3d1fade9a547bbbfb4ef395812fcf63b69caeda2e7f4f35dd27",
+    "sha256": "0ceb77bf00d3592247e1e895bb73db07beb04f8414502adff5ee37a03dd4ccc0",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "product": {"fetch_kib": 863582.5417, "write_kib": 589824.0, "valu_insts": 382697472},
-    "forward": {"fetch_kib": 277789.9583, "write_kib": 524288.2083, "valu_insts": 141918208},
+    "product": {"fetch_kib": 887933.6, "write_kib": 540672.0, "valu_insts": 394428416},
+    "forward": {"fetch_kib": 290376.7, "write_kib": 573440.3, "valu_insts": 145096704},
 }
 
 # VALU issue capacity: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at 2.4 GHz
@@ -126,7 +126,7 @@ def cpu_baseline(N, moduli, psis, budget_s=12.0):
         el = time.perf_counter() - t0
         if el >= budget_s:
             break
-    return {"value": done / el, "unit": "NTT/s", "cores": threads, "kind": "oracle",
+    return {"value": done / el, "unit": "NTT/s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": "%d limb forward transforms (N=%d, first %d of the 8 primes), O(N^2) direct "
                       "definition, %d threads, %.1f s" % (done, N, min(done, len(moduli)), threads, el)}
 
@@ -301,10 +301,12 @@ def run_served(nt, pool, moduli, mode, rate, n, streams=2, wide_min=0, wide_max=
             "submit_margin_ms": round(-late / 1e6, 1)}
 
 
-def time_serving(nt, torch, primes, rates=SERVE_RATES, max_requests=4000, seconds=1.0,
+def time_serving(nt, torch, primes, rates=SERVE_RATES, max_requests=20000, seconds=2.0,
                  modes=("batched", "batched_persistent_only", "fifo", "fifo_per_limb")):
-    """Open-loop sweep over arrival rates for each serving form; the per-limb FIFO form (about 850
-    req/s at best) is swept only up to 5k req/s, where it is already saturated."""
+    """Open-loop sweep over arrival rates for each serving form: min(max_requests, rate x seconds)
+    requests per rate, so 20k requests from 10k req/s up; the per-limb FIFO form (about 900
+    req/s at best) is swept only up to 5k req/s with at most 2000 requests, where it is already
+    saturated."""
     moduli = primes["serving"]["moduli"]
     pool = OperandPool(torch, moduli)
     code = {"batched": (nt.SERVE_BATCHED, 0, 0), "batched_persistent_only": (nt.SERVE_BATCHED, 18, 0),
@@ -320,7 +322,7 @@ def time_serving(nt, torch, primes, rates=SERVE_RATES, max_requests=4000, second
         for r in rates:
             if m == "fifo_per_limb" and r > 5000:
                 continue
-            n = int(min(max_requests, r * seconds))
+            n = int(min(max_requests if m != "fifo_per_limb" else 2000, r * seconds))
             runs.append(run_served(nt, pool, moduli, code[m][0], r, n, wide_min=code[m][1], wide_max=code[m][2]))
             print("serve %s rate %d: p50 %.2f ms p99 %.2f ms, %.0f req/s" %
                   (m, r, runs[-1]["p50_ms"], runs[-1]["p99_ms"], runs[-1]["throughput_rps"]), file=sys.stderr,
@@ -379,6 +381,78 @@ def time_small_primes(nt, torch, primes, key="small_16384", B=512, steps=100, wa
             "product_ms": round(prod_ms, 4),
             "product_hbm_frac": round(prod_bytes / (prod_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "fwd_limb_ntts_per_s": round(limbs / (fwd_ms * 1e-3), 1)}
+
+
+def time_plain_step(nt, torch, a, b, N, moduli, B, reps=2):
+    """The headline step in the plain per-call form: for every limb, forward(a) 1 -> 4,
+    forward(b) 1 -> 4, the element-wise multiply (input factor 4) and the inverse 1 -> 1, each
+    its own launch on one stream (4 launches per limb), then the add into acc."""
+    L = len(moduli)
+    stream = torch.cuda.current_stream()
+    fa, fb = torch.empty_like(a), torch.empty_like(a)
+    acc = torch.zeros_like(a)
+
+    views = []
+    for p in range(B):
+        for l, q in enumerate(moduli):
+            s = slice((p * L + l) * N, (p * L + l + 1) * N)
+            views.append((q, a[s], b[s], fa[s], fb[s], acc[s]))
+
+    def step():
+        for q, av, bv, fav, fbv, accv in views:
+            nt.ntt_forward(fav, av, N, q, 1, 4, stream=stream)
+            nt.ntt_forward(fbv, bv, N, q, 1, 4, stream=stream)
+            nt.eltwise_mult_mod(fav, fav, fbv, N, q, 4, stream=stream)
+            nt.ntt_inverse(fav, fav, N, q, 1, 1, stream=stream)
+            nt.eltwise_add_mod(accv, accv, fav, N, q, stream=stream)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    return {"form": "one launch per limb-transform and per element-wise op (5 per limb), one stream",
+            "ms_per_step": round(ms, 2), "forward_ntts_per_s": round(2 * B * L / (ms * 1e-3), 1),
+            "launches_per_step": 5 * B * L}
+
+
+def time_eltwise(nt, torch, a, b, N, moduli, B, reps=20):
+    """eltwise_mult_mod (input factor 1) and eltwise_add_mod over the headline's arrays
+    (B x 8 limbs of N = 2^14): 24 algorithmic bytes per element (two reads, one write)."""
+    stream = torch.cuda.current_stream()
+    c = torch.empty_like(a)
+    n = a.numel()
+    out = {}
+    for name, fn in (("eltwise_mult_mod", lambda: nt.eltwise_mult_mod_rns(c, a, b, N, moduli, B, 1, stream=stream)),
+                     ("eltwise_add_mod", lambda: nt.eltwise_add_mod_rns(c, a, b, N, moduli, B, stream=stream))):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = 24 * n / (ms * 1e-3) / 1e9
+        out[name] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_ms": round(ms, 4), "elements": n,
+                     "alg_bytes": 24 * n}
+    del c
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def time_copy(torch, words=1 << 27, reps=10):
@@ -442,13 +516,15 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sweep")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving sweep (full size)")
-    ap.add_argument("--serve-requests", type=int, default=4000, help="cap on requests per arrival rate")
-    ap.add_argument("--serve-seconds", type=float, default=1.0, help="arrival window per rate")
+    ap.add_argument("--serve-requests", type=int, default=20000, help="cap on requests per arrival rate")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window per rate")
     ap.add_argument("--serve-modes", default="batched,batched_persistent_only,fifo,fifo_per_limb",
                     help="comma-separated serving forms (batched_capK: batched with K wide launches per stream)")
     ap.add_argument("--large-ring-only", type=int, default=0, metavar="B",
                     help="only time the N = 2^16 x 32-limb forward and inverse at B polynomials per launch "
                          "(for profiling the two-pass kernels)")
+    ap.add_argument("--uneven-only", action="store_true",
+                    help="only time the uneven batch (256 polynomials, N in 2^12..2^15) as one persistent launch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 4 times (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -473,6 +549,10 @@ def main():
     if args.large_ring_only:
         print(json.dumps({"large_ring_n65536_l32": time_large_ring(nt, torch, load_primes(),
                                                                    batches=(args.large_ring_only,))}), flush=True)
+        return
+
+    if args.uneven_only:
+        print(json.dumps({"uneven_batch_256polys": time_uneven_batch(nt, torch, load_primes())}), flush=True)
         return
 
     if args.serve_only:
@@ -578,6 +658,8 @@ def main():
         "products_per_s": round(limbs / (wall / args.steps), 1),
     }
     if not args.no_extra:
+        out["eltwise_n16384_l8x%d" % B] = time_eltwise(nt, torch, a, b, N, moduli, B)
+        out["plain_per_call_step"] = time_plain_step(nt, torch, a, b, N, moduli, B)
         del a, b, c, ws, acc
         torch.cuda.empty_cache()
         out["hbm_copy"] = time_copy(torch)
@@ -590,9 +672,44 @@ def main():
         if not args.no_serve:
             out["serving"] = time_serving(nt, torch, load_primes(), max_requests=args.serve_requests,
                                           seconds=args.serve_seconds, modes=tuple(args.serve_modes.split(",")))
+    out["summary"] = summary(out)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, moduli, psis, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def summary(out):
+    """The secondary figures in one short object near the end of the line, where a reader of the
+    output's tail sees them: the forward-only batched launch and its roofline, the plain
+    per-call step, the large ring against its 50%-of-HBM target, the uneven batch, the word-size
+    2^32 steps, the element-wise rooflines and the serving forms' best rates at p99 <= 10 ms."""
+    s = {"forward_only_launch": {"limb_ntts_per_s": out.get("fwd_ntt_rate"),
+                                 "hbm_frac": (out.get("roofline_fwd") or {}).get("frac"),
+                                 "avg_ms": (out.get("roofline_fwd") or {}).get("avg_ms")}}
+    if "plain_per_call_step" in out:
+        p = out["plain_per_call_step"]
+        s["plain_per_call_step"] = {"ms_per_step": p["ms_per_step"], "forward_ntts_per_s": p["forward_ntts_per_s"],
+                                    "batched_step_speedup": round(p["ms_per_step"] / out["ms_per_step"], 1)}
+    lr = out.get("large_ring_n65536_l32")
+    if lr:
+        s["large_ring_n65536_l32"] = {k: {"fwd_us_per_launch": v["fwd_us"], "fwd_hbm_frac": v["fwd_hbm_frac"],
+                                          "inv_us_per_launch": v["inv_us"]}
+                                      for k, v in lr.items() if k.startswith("B")}
+        s["large_ring_n65536_l32"]["target"] = "B1 forward <= 16.8 us (0.50 of 8 TB/s on 64 MiB)"
+    ub = out.get("uneven_batch_256polys")
+    if ub:
+        s["uneven_batch_256polys"] = {k: ub[k] for k in ("fwd_batched_us", "fwd_graph_us", "fwd_batched_hbm_frac",
+                                                         "fwd_per_call_us", "inv_batched_us") if k in ub}
+    for k in ("small_primes_n16384_l8", "small_primes_n32768_l8", "small_primes_n65536_l8"):
+        if k in out:
+            s[k] = {"forward_ntts_per_s": out[k]["forward_ntts_per_s"], "ms_per_step": out[k]["ms_per_step"]}
+    e = [k for k in out if k.startswith("eltwise_")]
+    if e:
+        s["eltwise"] = {n: {"frac": v["frac"], "achieved_gbs": v["achieved"]} for n, v in out[e[0]].items()}
+    sv = out.get("serving")
+    if sv:
+        s["serving_max_rate_p99_le_10ms"] = {m: v["max_rate_p99_le_10ms"] for m, v in sv.items() if isinstance(v, dict)}
+    return s
 
 
 if __name__ == "__main__":

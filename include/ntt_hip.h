@@ -540,7 +540,7 @@ typedef struct {
                                     launches of the two-pass kernels on `streams` extra streams;
                                     0 = 15, 18 = never (all requests in persistent launches) */
   uint32_t wide_max_inflight;    /* such launches in flight per wide stream before further large
-                                    requests join the persistent launches; 0 = 8, at most 1024 */
+                                    requests join the persistent launches; 0 = 2, at most 1024 */
 } ntt_server_config;
 typedef struct {
   uint64_t N;

@@ -606,7 +606,7 @@ ntt_status ntt_server_create(ntt_server** out, const ntt_server_config* config) 
   if (c.max_batch_tasks < NTT_MAX_LIMBS || c.max_batch_tasks > (1u << 20)) return NTT_EINVAL_COUNT;
   if (c.max_queue == 0) c.max_queue = 1u << 20;
   if (c.wide_min_log_degree == 0) c.wide_min_log_degree = kMaxOnchipLog + 1;
-  if (c.wide_max_inflight == 0) c.wide_max_inflight = 8;
+  if (c.wide_max_inflight == 0) c.wide_max_inflight = 2;
   if (c.wide_max_inflight > 1024) return NTT_EINVAL_COUNT;
   if (c.wide_min_log_degree < 10 || c.wide_min_log_degree > NTT_MAX_LOG_DEGREE + 1) return NTT_EINVAL_COUNT;
   c.hbm_budget = align_up(c.hbm_budget);
