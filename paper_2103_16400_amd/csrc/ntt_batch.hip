@@ -1,20 +1,25 @@
-// Persistent batch kernel: one launch runs a list of limb tasks of mixed ring
-// degree (2^10 .. 2^17), moduli and operation.
+// Persistent batch kernel: one launch (two for two-pass sizes) runs a list of
+// limb tasks of mixed ring degree (2^10 .. 2^17), moduli and operation.
 //
 // RNS polynomials of different sizes and limb counts (Section 5) decompose
-// into independent limb tasks.  Each workgroup of the persistent grid claims
-// the next task from a device-side counter (tasks are ordered largest first)
-// and runs it to completion by itself, so tasks never wait on each other:
-//   * N <= 2^14: the single-pass transform held on chip (ntt_onchip.h), with
-//     2^(logN-9) coefficients per thread so every size uses 512 threads;
-//   * N >= 2^15: both passes of the two-pass transform (ntt_tile.h), one
-//     4096-coefficient tile at a time; the intermediate stays in the limb's
-//     output buffer and the workgroup barrier orders the passes.
-// Operations: forward (lazy [0, 4q) or canonical), inverse (lazy [0, 2q) or
-// canonical) and the negacyclic product out = a * b of the Section 4 listing
-// (forward(a), forward(b) fused with the multiply, inverse).  The task list
-// and its length live in device memory, so a captured graph of
-// [descriptor copy, counter reset, kernel] can be replayed for any batch.
+// into independent limb tasks.  The host groups the tasks into blocks of one
+// class (operation, N, wide-range flag), longest units first and by (N, q)
+// within a class; each workgroup of the persistent grid claims the next unit
+// from a device-side counter and runs the units of that block until a claim
+// lands in the next block:
+//   * N <= 2^14: whole limbs held on chip (ntt_onchip.h) with the single-pass
+//     kernel's own shape (16 or 32 coefficients per thread), 512 / (N / 2^logr)
+//     limbs side by side per workgroup;
+//   * N >= 2^15 transforms: 4096-coefficient tiles of the two-pass schedule
+//     (ntt_tile.h), two per workgroup; the first pass runs in phase 0, the
+//     last pass in a second launch (phase 1), whose boundary orders the two;
+//   * products out = a * b (forward(a), forward(b) fused with the multiply,
+//     inverse: the product listing of Section 4): on chip for N <= 2^14, else
+//     one workgroup runs all three two-pass transforms.
+// Forward outputs are lazy [0, 4q) or canonical, inverse outputs lazy [0, 2q)
+// or canonical.  The blocks, the descriptors and their counts live in device
+// memory, so a captured graph of [descriptor copy, counter reset, phase 0,
+// phase 1] can be replayed for any batch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -50,39 +55,187 @@ struct ntt_batch {
 
 namespace nttamd {
 
-// Staging layout: [0, 128) count word; tasks from byte 128.  The device copy
-// keeps the claim counter in its own line in front: counter at 0, staging
-// mirrored from byte 128.
-constexpr size_t kStageHead = 128;
+// Block classes: BatchBlock::cls = kind | logN << 3 | op << 8 | wide << 11.
+enum : uint32_t { kClassOnchip = 0, kClassProduct = 1, kClassTile0 = 2, kClassTile1 = 3 };
+// A run of units of one class within a phase.
+struct BatchBlock {
+  uint32_t unit0, units;    // claim indices [unit0, unit0 + units) of the phase
+  uint32_t desc0, subs;     // first descriptor; sub-tasks (limbs, or tiles: N / 4096 per descriptor)
+  uint32_t cls, pad[3];
+};
+// Every class present in a batch has one block per phase it runs in: at most
+// 40 single-pass transform classes, 13 product classes and 12 two-pass
+// transform classes in phase 0, and those 12 again in phase 1.
+constexpr int kMaxBlocks = 80;
+struct BatchHead {
+  uint32_t units[2];        // per phase
+  uint32_t blocks[2];       // per phase; phase 1's blocks follow phase 0's
+  uint32_t pad[4];
+  BatchBlock block[kMaxBlocks];
+};
+
+// Staging layout: the head, then one descriptor per task from kStageHead on.
+// The device copy keeps the two claim counters in their own line in front
+// (counters at 0, staging mirrored from kDevHead).
+constexpr size_t kStageHead = (sizeof(BatchHead) + 127) & ~(size_t)127;
 constexpr size_t kDevHead = 128;
 static ntt_batch_stage& cur_stage(ntt_batch* b) { return b->stage[b->cur]; }
 static BatchTask* staged_tasks(ntt_batch* b) { return reinterpret_cast<BatchTask*>(cur_stage(b).host + kStageHead); }
+static BatchHead* staged_head(ntt_batch* b) { return reinterpret_cast<BatchHead*>(cur_stage(b).host); }
 static size_t stage_bytes(size_t count) { return kStageHead + count * sizeof(BatchTask); }
+static size_t dev_bytes(const ntt_batch* b) { return kDevHead + stage_bytes(b->capacity); }
 
 constexpr int kBatchThreads = 512;
-constexpr int kBatchLdsWords32 = (1 << 14) + (1 << 14) / 32;   // 2^14 split exchange, 66 KiB
+// LDS of one workgroup: two sub-groups' 4096-coefficient tiles, or the exchange
+// buffers of the limbs it holds (68 KiB; two workgroups share a CU).
+constexpr int kBatchLdsWords32 = 17408;
 
-// ---- one task -----------------------------------------------------------------
+// ---- block classes --------------------------------------------------------------
+//
+// The host orders the tasks into blocks of one class each (kind, logN, op,
+// wide-range flag).  A claimed unit of a block is G sub-tasks run side by side
+// by G sub-groups of 512 / G threads: whole limbs (N <= 2^14) with the
+// single-pass kernel's own shape, 2^onchip_logr(logN) coefficients per thread;
+// or two 4096-coefficient tiles of one pass of a split two-pass transform.
 
+__host__ __device__ constexpr int onchip_groups(int logN) { return kBatchThreads / ((1 << logN) >> onchip_logr(logN)); }
+
+// Every sub-group is a whole number of waves, so the sub-task index, the
+// descriptor and its plan are wave-uniform: taken through readfirstlane they
+// live in scalar registers, as a kernel's arguments would.
+// (The builtin returns a signed int: widened directly, a low word with bit 31
+// set would sign-extend over the high word.)
+__device__ __forceinline__ u32 rfl(u32 v) { return (u32)__builtin_amdgcn_readfirstlane((int)v); }
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint64_t lo = rfl((u32)v), hi = rfl((u32)(v >> 32));
+  return reinterpret_cast<T*>(lo | hi << 32);
+}
+// Address-space views for a device function (the compiler infers them only
+// for pointers that come from a kernel's arguments): descriptors and plan
+// headers are read-only during a launch and read through the constant space
+// (scalar loads), coefficients and tables through the global space.
+#define NTTAMD_CONST __attribute__((address_space(4)))
+#define NTTAMD_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T* as_global(T* p) {
+  return (T*)(NTTAMD_GLOBAL T*)p;
+}
+__device__ __forceinline__ BatchTask load_task(const BatchTask* tasks, u32 i) {
+  const NTTAMD_CONST BatchTask* c = (const NTTAMD_CONST BatchTask*)uniform_ptr(tasks);
+  BatchTask t;
+  t.out = as_global(c[i].out);
+  t.in = as_global(c[i].in);
+  t.in2 = as_global(c[i].in2);
+  t.tmp = as_global(c[i].tmp);
+  t.plan = c[i].plan;
+  t.logN = c[i].logN;
+  t.op = c[i].op;
+  return t;
+}
+__device__ __forceinline__ PlanView load_plan_batch(const u64* plan, bool fwd, u64 N) {
+  const NTTAMD_CONST PlanHeader* h = (const NTTAMD_CONST PlanHeader*)plan;
+  PlanView v;
+  v.q = h->q;
+  v.q2 = h->q2;
+  v.nq = h->nq;
+  v.nq2 = 0 - h->q2;
+  v.ninv = h->ninv;
+  v.ninv_p = h->ninv_p;
+  v.wn = h->wn;
+  v.wn_p = h->wn_p;
+  v.bk = h->barrett_k;
+  v.qbits = (u32)h->qbits;
+  v.q3 = h->q + h->q2;
+  v.q4 = 2 * h->q2;
+  v.nq4 = 0 - v.q4;
+  v.rq = h->barrett_k >> (v.qbits - 1);
+  v.tw = reinterpret_cast<const ulonglong2*>(as_global(plan) + kPlanHeaderWords) + (fwd ? 0 : N);
+  v.twp = v.tw + 2 * N;
+  return v;
+}
+
+// Runs the units of block bk from the claimed unit u on, claiming the next unit
+// after each, and returns the first claimed unit outside the block.  body(k, t,
+// active, h) runs sub-task k with sub-group thread t in sub-group h; a
+// sub-group past the block's last sub-task repeats the unit's first one with
+// active false (every barrier is still reached, nothing is stored).
+template <typename F>
+__device__ __forceinline__ u32 run_block(const BatchBlock& bk_in, u32* ctr_in, u32* claimed_in, u32 u, u32 g, F&& body) {
+  const u32 unit0 = rfl(bk_in.unit0), units = rfl(bk_in.units);
+  const u32 subs = rfl(bk_in.subs);
+  u32* ctr = uniform_ptr(ctr_in);
+  u32* claimed = uniform_ptr(claimed_in);
+  const u32 nt = kBatchThreads / g;             // a multiple of the wave size
+  const u32 h = rfl(threadIdx.x / nt), t = threadIdx.x % nt;
+#pragma unroll 1
+  for (;;) {
+    const u32 k0 = (u - unit0) * g;
+    const bool active = k0 + h < subs;
+    // the next claim is issued before this unit's work, which hides its latency
+    u32 next = 0;
+    if (threadIdx.x == 0) next = atomicAdd(ctr, 1u);
+    // a fresh view of t per unit: the per-thread address terms are recomputed
+    // inside the unit rather than held in registers across the loop
+    body(active ? k0 + h : k0, opaque(t), active, h);
+    __syncthreads();                            // LDS reuse, and every thread has read `claimed`
+    if (threadIdx.x == 0) *claimed = next;
+    __syncthreads();
+    u = rfl(*claimed);
+    if (u - unit0 >= units) return u;
+  }
+}
+
+// Whole single-pass transforms (N <= 2^14).
 template <bool FWD, int LOGN, int MODE, bool WIDE>
-__device__ __attribute__((noinline)) void task_onchip(const u64* plan, const u64* in, u64* out, const u64* mul, u32* lds,
-                                            bool nt) {
-  const PlanView pv = load_plan(plan, FWD, 1ull << LOGN);
-  onchip_body<FWD, LOGN, LOGN - 9, true, MODE, true, WIDE>(pv, in, out, mul, lds, nt);
+__device__ __attribute__((noinline)) u32 class_onchip(const BatchTask* tasks, const BatchBlock bk, u32* ctr,
+                                                      u32* claimed, u32 u, u32* lds) {
+  constexpr int LOGR = onchip_logr(LOGN);
+  constexpr bool SPLIT = LOGN >= 13;
+  using K = OnChip<FWD, LOGN, LOGR, SPLIT, true, WIDE>;
+  constexpr int G = onchip_groups(LOGN);
+  static_assert(G * K::LDSW * sizeof(typename K::W) <= kBatchLdsWords32 * 4, "sub-group exchange buffers exceed LDS");
+  return run_block(bk, ctr, claimed, u, G, [&](u32 k, u32 t, bool active, u32 h) {
+    const BatchTask tk = load_task(tasks, rfl(bk.desc0 + k));
+    const PlanView pv = load_plan_batch(tk.plan, FWD, 1ull << LOGN);
+    typename K::W* l = reinterpret_cast<typename K::W*>(lds) + h * K::LDSW;
+    onchip_body<FWD, LOGN, LOGR, SPLIT, MODE, true, WIDE, true>(pv, tk.in, tk.out, nullptr, l, true, t, active);
+  });
+}
+
+// Whole products on chip: out <- NTT(a) lazy, then out <- InvNTT(NTT(b) (.) out)
+// canonical (the product listing of Section 4).
+template <int LOGN, bool WIDE>
+__device__ __attribute__((noinline)) u32 class_product_onchip(const BatchTask* tasks, const BatchBlock bk, u32* ctr,
+                                                              u32* claimed, u32 u, u32* lds) {
+  constexpr int LOGR = onchip_logr(LOGN);
+  constexpr bool SPLIT = LOGN >= 13;
+  using K = OnChip<true, LOGN, LOGR, SPLIT, true, WIDE>;
+  constexpr int G = onchip_groups(LOGN);
+  static_assert(G * K::LDSW * sizeof(typename K::W) <= kBatchLdsWords32 * 4, "sub-group exchange buffers exceed LDS");
+  return run_block(bk, ctr, claimed, u, G, [&](u32 k, u32 t, bool active, u32 h) {
+    const BatchTask tk = load_task(tasks, rfl(bk.desc0 + k));
+    const PlanView pf = load_plan_batch(tk.plan, true, 1ull << LOGN);
+    typename K::W* l = reinterpret_cast<typename K::W*>(lds) + h * K::LDSW;
+    onchip_body<true, LOGN, LOGR, SPLIT, kOutLazy, true, WIDE, true>(pf, tk.in, tk.out, nullptr, l, true, t, active);
+    __syncthreads();                            // NTT(a) in out, read back by other threads of the sub-group
+    const PlanView pi = load_plan_batch(tk.plan, false, 1ull << LOGN);
+    onchip_product_body<LOGN, LOGR, SPLIT, kOutCanon, true, WIDE, true>(pf, pi, tk.in2, tk.out, tk.out, l, true, t, active);
+  });
 }
 
 // Both passes of a two-pass transform by one workgroup (512 threads, tiles of
-// 4096 coefficients, 8 per thread).
-// `mid` receives the first pass (may equal out unless out holds the multiplier).
+// 4096 coefficients, 8 per thread); `mid` receives the first pass.
 template <bool FWD, int LOGN, int MODE>
-__device__ __attribute__((noinline)) void task_twopass(const u64* plan, const u64* in, u64* mid, u64* out, const u64* mul,
-                                             u64* lds, bool nt) {
+__device__ __forceinline__ void twopass_whole(const PlanView& pv, const u64* in, u64* mid, u64* out, const u64* mul,
+                                              u64* lds, bool nt) {
   constexpr int LT_LO = mp_logt_lo(LOGN);
   constexpr int LT_HI = LOGN - LT_LO;
   constexpr int LC_HI = 12 - LT_HI;           // columns per high-pass tile
   constexpr int LH_LO = 12 - LT_LO;           // blocks per low-pass tile
   constexpr int TILES = 1 << (LOGN - 12);
-  const PlanView pv = load_plan(plan, FWD, 1ull << LOGN);
+  const u32 t = threadIdx.x;
 #pragma unroll 1
   for (int step = 0; step < 2; ++step) {
     const bool hi = FWD ? step == 0 : step == 1;
@@ -92,100 +245,177 @@ __device__ __attribute__((noinline)) void task_twopass(const u64* plan, const u6
 #pragma unroll 1
     for (u32 tile = 0; tile < (u32)TILES; ++tile) {
       if (hi) {
-        if (last) tile_body<FWD, LT_HI, 3, LC_HI, 0, MODE, true, -1, true>(pv, LOGN, LT_LO, tile, src, dst, mul, lds, false);
-        else tile_body<FWD, LT_HI, 3, LC_HI, 0, kOutLazy, false, -1, true>(pv, LOGN, LT_LO, tile, src, dst, mul, lds, nt);
+        if (last) tile_body<FWD, LT_HI, 3, LC_HI, 0, MODE, true, -1, true>(pv, LOGN, LT_LO, tile, src, dst, mul, lds, false, t, true);
+        else tile_body<FWD, LT_HI, 3, LC_HI, 0, kOutLazy, false, -1, true>(pv, LOGN, LT_LO, tile, src, dst, mul, lds, nt, t, true);
       } else {
-        if (last) tile_body<FWD, LT_LO, 3, 0, LH_LO, MODE, true, -1, true>(pv, LOGN, 0, tile, src, dst, mul, lds, false);
-        else tile_body<FWD, LT_LO, 3, 0, LH_LO, kOutLazy, false, -1, true>(pv, LOGN, 0, tile, src, dst, mul, lds, nt);
+        if (last) tile_body<FWD, LT_LO, 3, 0, LH_LO, MODE, true, -1, true>(pv, LOGN, 0, tile, src, dst, mul, lds, false, t, true);
+        else tile_body<FWD, LT_LO, 3, 0, LH_LO, kOutLazy, false, -1, true>(pv, LOGN, 0, tile, src, dst, mul, lds, nt, t, true);
       }
       __syncthreads();
     }
   }
 }
 
-// Second half of a product on chip: out = InvNTT(NTT(b) (.) out), canonical.
-template <int LOGN, bool WIDE>
-__device__ __attribute__((noinline)) void task_product_onchip(const u64* plan, const u64* b, u64* out, u32* lds) {
-  const PlanView pf = load_plan(plan, true, 1ull << LOGN);
-  const PlanView pi = load_plan(plan, false, 1ull << LOGN);
-  onchip_product_body<LOGN, LOGN - 9, true, kOutCanon, true, WIDE>(pf, pi, b, out, out, lds, true);
-}
-
-template <bool WIDE>
-__device__ __forceinline__ void run_product_onchip(u32 logN, const u64* plan, const u64* b, u64* out, void* lds) {
-  u32* l32 = reinterpret_cast<u32*>(lds);
-  switch (logN) {
-    case 10: task_product_onchip<10, WIDE>(plan, b, out, l32); break;
-    case 11: task_product_onchip<11, WIDE>(plan, b, out, l32); break;
-    case 12: task_product_onchip<12, WIDE>(plan, b, out, l32); break;
-    case 13: task_product_onchip<13, WIDE>(plan, b, out, l32); break;
-    case 14: task_product_onchip<14, WIDE>(plan, b, out, l32); break;
-    default: break;
-  }
-}
-
-// WIDE applies to the single-pass sizes only; two-pass tasks run the paper's butterflies.
-template <bool FWD, int MODE, bool WIDE>
-__device__ __forceinline__ void run_transform(u32 logN, const u64* plan, const u64* in, u64* mid, u64* out,
-                                              const u64* mul, void* lds, bool nt) {
-  u32* l32 = reinterpret_cast<u32*>(lds);
+// Whole products with N >= 2^15, one per workgroup: out <- NTT(a) lazy;
+// out <- NTT(b) (.) out (first pass of NTT(b) in tmp); out <- InvNTT(out).
+template <int LOGN>
+__device__ __attribute__((noinline)) u32 class_product_twopass(const BatchTask* tasks, const BatchBlock bk, u32* ctr,
+                                                               u32* claimed, u32 u, u32* lds) {
   u64* l64 = reinterpret_cast<u64*>(lds);
+  return run_block(bk, ctr, claimed, u, 1, [&](u32 k, u32, bool, u32) {
+    const BatchTask tk = load_task(tasks, rfl(bk.desc0 + k));
+    const PlanView pf = load_plan_batch(tk.plan, true, 1ull << LOGN);
+    twopass_whole<true, LOGN, kOutLazy>(pf, tk.in, tk.out, tk.out, nullptr, l64, true);
+    twopass_whole<true, LOGN, kOutMul>(pf, tk.in2, tk.tmp, tk.out, tk.out, l64, true);
+    const PlanView pi = load_plan_batch(tk.plan, false, 1ull << LOGN);
+    twopass_whole<false, LOGN, kOutCanon>(pi, tk.out, tk.out, tk.out, nullptr, l64, false);
+  });
+}
+
+// Tiles of one pass (PASS 0: in -> out, lazy; PASS 1: out -> out with the output
+// MODE) of split two-pass transforms: two 4096-coefficient tiles per unit, 256
+// threads and 16 coefficients each, the multi-pass kernels' own tile shape (the
+// low pass reads the transposed sub-tables).  Sub-task k is tile k mod T of the
+// block's task k / T, T = N / 4096.
+template <bool FWD, int LOGN, int MODE, int PASS>
+__device__ __attribute__((noinline)) u32 class_tile(const BatchTask* tasks, const BatchBlock bk, u32* ctr,
+                                                    u32* claimed, u32 u, u32* lds) {
+  constexpr int LT_LO = mp_logt_lo(LOGN);
+  constexpr int LT_HI = LOGN - LT_LO;
+  constexpr int LC_HI = 12 - LT_HI;
+  constexpr int LH_LO = 12 - LT_LO;
+  constexpr int TSH = LOGN - 12;
+  constexpr bool HI = FWD ? PASS == 0 : PASS == 1;
+  constexpr int PTOP = mp_perm_top(FWD, LOGN);
+  constexpr int TILE_LDS = (4096 + 256);      // u64 words of one tile's exchange buffer at 16 per thread
+  static_assert(2 * TILE_LDS * 2 <= kBatchLdsWords32, "tile exchange buffers exceed LDS");
+  return run_block(bk, ctr, claimed, u, 2, [&](u32 k, u32 t, bool active, u32 h) {
+    const BatchTask tk = load_task(tasks, rfl(bk.desc0 + (k >> TSH)));
+    const u32 tile = rfl(k & ((1u << TSH) - 1u));
+    const PlanView pv = load_plan_batch(tk.plan, FWD, 1ull << LOGN);
+    u64* l = reinterpret_cast<u64*>(lds) + h * TILE_LDS;
+    if constexpr (HI) {
+      if constexpr (PASS == 0)
+        tile_body<FWD, LT_HI, kMpLogrLo, LC_HI, 0, kOutLazy, false, -1, true>(pv, LOGN, LT_LO, tile, tk.in, tk.out, nullptr, l, true, t, active);
+      else
+        tile_body<FWD, LT_HI, kMpLogrLo, LC_HI, 0, MODE, true, -1, true>(pv, LOGN, LT_LO, tile, tk.out, tk.out, nullptr, l, false, t, active);
+    } else {
+      if constexpr (PASS == 0)
+        tile_body<FWD, LT_LO, kMpLogrLo, 0, LH_LO, kOutLazy, false, PTOP, true>(pv, LOGN, 0, tile, tk.in, tk.out, nullptr, l, true, t, active);
+      else
+        tile_body<FWD, LT_LO, kMpLogrLo, 0, LH_LO, MODE, true, PTOP, true>(pv, LOGN, 0, tile, tk.out, tk.out, nullptr, l, false, t, active);
+    }
+  });
+}
+
+// A block of a class this kernel does not know: claims past it.
+__device__ __attribute__((noinline)) u32 class_skip(const BatchBlock bk, u32* ctr, u32* claimed, u32 u) {
+  return run_block(bk, ctr, claimed, u, 1, [](u32, u32, bool, u32) {});
+}
+
+template <bool FWD, int MODE, bool WIDE>
+__device__ __forceinline__ u32 pick_onchip(u32 logN, const BatchTask* tasks, const BatchBlock& bk, u32* ctr,
+                                           u32* claimed, u32 u, u32* lds) {
   switch (logN) {
-    case 10: task_onchip<FWD, 10, MODE, WIDE>(plan, in, out, mul, l32, nt); break;
-    case 11: task_onchip<FWD, 11, MODE, WIDE>(plan, in, out, mul, l32, nt); break;
-    case 12: task_onchip<FWD, 12, MODE, WIDE>(plan, in, out, mul, l32, nt); break;
-    case 13: task_onchip<FWD, 13, MODE, WIDE>(plan, in, out, mul, l32, nt); break;
-    case 14: task_onchip<FWD, 14, MODE, WIDE>(plan, in, out, mul, l32, nt); break;
-    case 15: task_twopass<FWD, 15, MODE>(plan, in, mid, out, mul, l64, nt); break;
-    case 16: task_twopass<FWD, 16, MODE>(plan, in, mid, out, mul, l64, nt); break;
-    case 17: task_twopass<FWD, 17, MODE>(plan, in, mid, out, mul, l64, nt); break;
-    default: break;
+    case 10: return class_onchip<FWD, 10, MODE, WIDE>(tasks, bk, ctr, claimed, u, lds);
+    case 11: return class_onchip<FWD, 11, MODE, WIDE>(tasks, bk, ctr, claimed, u, lds);
+    case 12: return class_onchip<FWD, 12, MODE, WIDE>(tasks, bk, ctr, claimed, u, lds);
+    case 13: return class_onchip<FWD, 13, MODE, WIDE>(tasks, bk, ctr, claimed, u, lds);
+    case 14: return class_onchip<FWD, 14, MODE, WIDE>(tasks, bk, ctr, claimed, u, lds);
+    default: return class_skip(bk, ctr, claimed, u);
   }
 }
 
-template <bool WIDE>
-__device__ __forceinline__ void run_task(const BatchTask& tk, void* lds) {
-  switch (tk.op & kBatchOpMask) {
-    case kBatchFwdLazy: run_transform<true, kOutLazy, WIDE>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true); break;
-    case kBatchFwdCanon: run_transform<true, kOutCanon, WIDE>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true); break;
-    case kBatchInvLazy: run_transform<false, kOutLazy, WIDE>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true); break;
-    case kBatchInvCanon: run_transform<false, kOutCanon, WIDE>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true); break;
-    case kBatchProduct:
-      // out <- NTT(a) lazy; out <- NTT(b) (.) out (first pass of NTT(b) in tmp); out <- InvNTT(out)
-      run_transform<true, kOutLazy, WIDE>(tk.logN, tk.plan, tk.in, tk.out, tk.out, nullptr, lds, true);
-      __syncthreads();
-      if (tk.logN <= (u32)kMaxOnchipLog) {        // the rest on chip, in one step
-        run_product_onchip<WIDE>(tk.logN, tk.plan, tk.in2, tk.out, lds);
-        break;
+template <bool FWD, int MODE, int PASS>
+__device__ __forceinline__ u32 pick_tile(u32 logN, const BatchTask* tasks, const BatchBlock& bk, u32* ctr,
+                                         u32* claimed, u32 u, u32* lds) {
+  switch (logN) {
+    case 15: return class_tile<FWD, 15, MODE, PASS>(tasks, bk, ctr, claimed, u, lds);
+    case 16: return class_tile<FWD, 16, MODE, PASS>(tasks, bk, ctr, claimed, u, lds);
+    case 17: return class_tile<FWD, 17, MODE, PASS>(tasks, bk, ctr, claimed, u, lds);
+    default: return class_skip(bk, ctr, claimed, u);
+  }
+}
+
+template <int PASS>
+__device__ __forceinline__ u32 pick_tile_op(u32 op, u32 logN, const BatchTask* tasks, const BatchBlock& bk, u32* ctr,
+                                            u32* claimed, u32 u, u32* lds) {
+  switch (op) {
+    case kBatchFwdLazy: return pick_tile<true, kOutLazy, PASS>(logN, tasks, bk, ctr, claimed, u, lds);
+    case kBatchFwdCanon: return pick_tile<true, kOutCanon, PASS>(logN, tasks, bk, ctr, claimed, u, lds);
+    case kBatchInvLazy: return pick_tile<false, kOutLazy, PASS>(logN, tasks, bk, ctr, claimed, u, lds);
+    case kBatchInvCanon: return pick_tile<false, kOutCanon, PASS>(logN, tasks, bk, ctr, claimed, u, lds);
+    default: return class_skip(bk, ctr, claimed, u);
+  }
+}
+
+__device__ __forceinline__ u32 run_class(const BatchTask* tasks, const BatchBlock& bk, u32* ctr, u32* claimed, u32 u,
+                                         u32* lds) {
+  const u32 kind = bk.cls & 7u, logN = (bk.cls >> 3) & 31u, op = (bk.cls >> 8) & 7u;
+  const bool wide = (bk.cls >> 11) & 1u;
+  switch (kind) {
+    case kClassOnchip:
+      switch (op) {
+        case kBatchFwdLazy:
+          return wide ? pick_onchip<true, kOutLazy, true>(logN, tasks, bk, ctr, claimed, u, lds)
+                      : pick_onchip<true, kOutLazy, false>(logN, tasks, bk, ctr, claimed, u, lds);
+        case kBatchFwdCanon:
+          return wide ? pick_onchip<true, kOutCanon, true>(logN, tasks, bk, ctr, claimed, u, lds)
+                      : pick_onchip<true, kOutCanon, false>(logN, tasks, bk, ctr, claimed, u, lds);
+        case kBatchInvLazy:
+          return wide ? pick_onchip<false, kOutLazy, true>(logN, tasks, bk, ctr, claimed, u, lds)
+                      : pick_onchip<false, kOutLazy, false>(logN, tasks, bk, ctr, claimed, u, lds);
+        case kBatchInvCanon:
+          return wide ? pick_onchip<false, kOutCanon, true>(logN, tasks, bk, ctr, claimed, u, lds)
+                      : pick_onchip<false, kOutCanon, false>(logN, tasks, bk, ctr, claimed, u, lds);
+        default: return class_skip(bk, ctr, claimed, u);
       }
-      run_transform<true, kOutMul, false>(tk.logN, tk.plan, tk.in2, tk.tmp, tk.out, tk.out, lds, true);
-      __syncthreads();
-      run_transform<false, kOutCanon, false>(tk.logN, tk.plan, tk.out, tk.out, tk.out, nullptr, lds, false);
-      break;
-    default: break;
+    case kClassProduct:
+      switch (logN) {
+        case 10: return wide ? class_product_onchip<10, true>(tasks, bk, ctr, claimed, u, lds) : class_product_onchip<10, false>(tasks, bk, ctr, claimed, u, lds);
+        case 11: return wide ? class_product_onchip<11, true>(tasks, bk, ctr, claimed, u, lds) : class_product_onchip<11, false>(tasks, bk, ctr, claimed, u, lds);
+        case 12: return wide ? class_product_onchip<12, true>(tasks, bk, ctr, claimed, u, lds) : class_product_onchip<12, false>(tasks, bk, ctr, claimed, u, lds);
+        case 13: return wide ? class_product_onchip<13, true>(tasks, bk, ctr, claimed, u, lds) : class_product_onchip<13, false>(tasks, bk, ctr, claimed, u, lds);
+        case 14: return wide ? class_product_onchip<14, true>(tasks, bk, ctr, claimed, u, lds) : class_product_onchip<14, false>(tasks, bk, ctr, claimed, u, lds);
+        case 15: return class_product_twopass<15>(tasks, bk, ctr, claimed, u, lds);
+        case 16: return class_product_twopass<16>(tasks, bk, ctr, claimed, u, lds);
+        case 17: return class_product_twopass<17>(tasks, bk, ctr, claimed, u, lds);
+        default: return class_skip(bk, ctr, claimed, u);
+      }
+    case kClassTile0: return pick_tile_op<0>(op, logN, tasks, bk, ctr, claimed, u, lds);
+    case kClassTile1: return pick_tile_op<1>(op, logN, tasks, bk, ctr, claimed, u, lds);
+    default: return class_skip(bk, ctr, claimed, u);
   }
 }
 
+// Clears the two claim counters (a kernel, not a memset, so that a captured
+// graph replays it faithfully).
 __global__ void batch_reset_kernel(u32* counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+  if (threadIdx.x < 2) counter[threadIdx.x] = 0;
 }
 
+// One phase of a batch.  Phase 0 runs the whole tasks and the first pass of
+// every split two-pass transform, phase 1 the last passes: the launch boundary
+// orders the two passes of a split transform, so no workgroup waits on another.
+// Units are claimed in increasing order, so each workgroup walks the phase's
+// blocks forwards.
 __global__ void __launch_bounds__(kBatchThreads, 4)
-    ntt_batch_kernel(const BatchTask* __restrict__ tasks, const u32* __restrict__ count, u32* counter) {
+    ntt_batch_kernel(const BatchTask* __restrict__ tasks, const BatchHead* __restrict__ head, u32* counter, u32 phase) {
   __shared__ u32 lds[kBatchLdsWords32];
   __shared__ u32 claimed;
-  const u32 n = *count;
+  const u32 b_first = phase ? head->blocks[0] : 0u;
+  const u32 b_end = b_first + head->blocks[phase];
+  u32* ctr = counter + phase;
+  if (threadIdx.x == 0) claimed = atomicAdd(ctr, 1u);
+  __syncthreads();
+  u32 u = rfl(claimed);
+  u32 b = b_first;
 #pragma unroll 1
   for (;;) {
-    if (threadIdx.x == 0) claimed = atomicAdd(counter, 1u);
-    __syncthreads();
-    const u32 i = claimed;
-    __syncthreads();
-    if (i >= n) break;                          // every wave of every workgroup reaches this exit
-    const BatchTask tk = tasks[i];
-    if (tk.op & kBatchWide) run_task<true>(tk, lds);
-    else run_task<false>(tk, lds);
-    __syncthreads();
+    while (b < b_end && u - head->block[b].unit0 >= head->block[b].units) ++b;
+    if (b >= b_end) break;                      // every wave of every workgroup reaches this exit
+    const BatchBlock bk = head->block[b];
+    u = run_class(tasks, bk, ctr, &claimed, u, lds);
   }
 }
 
@@ -237,6 +467,95 @@ static ntt_status wait_staging(ntt_batch* b) {
   return NTT_OK;
 }
 
+// Class of a task, sub-tasks per descriptor (log2) and sub-tasks per unit.
+struct TaskClass {
+  uint32_t cls, tshift, g;
+  uint64_t cost;            // time of one unit, in coefficient-stages per thread (orders the blocks)
+};
+static TaskClass classify(const BatchTask& t) {
+  const uint32_t op = t.op & kBatchOpMask;
+  const uint32_t wide = (t.op & kBatchWide) ? 1u : 0u;
+  const uint32_t logN = t.logN;
+  TaskClass c{};
+  if (logN <= (uint32_t)kMaxOnchipLog) {
+    const uint64_t per_thread = (uint64_t)1 << onchip_logr((int)logN);
+    c.g = (uint32_t)onchip_groups((int)logN);
+    if (op == kBatchProduct) {
+      c.cls = kClassProduct | logN << 3 | op << 8 | wide << 11;
+      c.cost = 3 * per_thread * logN;
+    } else {
+      c.cls = kClassOnchip | logN << 3 | op << 8 | wide << 11;
+      c.cost = per_thread * logN;
+    }
+  } else if (op == kBatchProduct) {
+    c.cls = kClassProduct | logN << 3 | op << 8;
+    c.g = 1;
+    c.cost = 3 * 8 * (uint64_t)logN << (logN - 12);   // three two-pass transforms of N / 4096 tiles each
+  } else {
+    c.cls = kClassTile0 | logN << 3 | op << 8;
+    c.tshift = logN - 12;
+    c.g = 2;
+    c.cost = 16 * (uint64_t)(logN + 1) / 2;
+  }
+  return c;
+}
+
+// Writes a task list into the current staging set as the two phases of one
+// batch: one descriptor per task, ordered by class (longest units first) and,
+// within a class, by (N, q), so that the workgroups running at one time share
+// twiddle tables in L2.  Two-pass transforms (N >= 2^15, not products) run as
+// tiles: the first pass in phase 0, the last pass in phase 1 (same
+// descriptors).  *staged = the number of descriptors.
+static ntt_status stage_units(ntt_batch* b, const std::vector<BatchTask>& list, size_t* staged) {
+  const size_t n = list.size();
+  std::vector<TaskClass> cl(n);
+  std::vector<size_t> order(n);
+  for (size_t k = 0; k < n; ++k) {
+    cl[k] = classify(list[k]);
+    order[k] = k;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+    if (cl[x].cost != cl[y].cost) return cl[x].cost > cl[y].cost;
+    if (cl[x].cls != cl[y].cls) return cl[x].cls < cl[y].cls;
+    return list[x].plan < list[y].plan;
+  });
+  BatchTask* dst = staged_tasks(b);
+  BatchHead* head = staged_head(b);
+  std::vector<BatchBlock> p0, p1;
+  for (size_t w = 0; w < n; ++w) {
+    const size_t k = order[w];
+    dst[w] = list[k];
+    const TaskClass& c = cl[k];
+    if (p0.empty() || p0.back().cls != c.cls) {
+      BatchBlock bk{};
+      bk.unit0 = p0.empty() ? 0u : p0.back().unit0 + p0.back().units;
+      bk.desc0 = (uint32_t)w;
+      bk.cls = c.cls;
+      p0.push_back(bk);
+    }
+    BatchBlock& bk = p0.back();
+    bk.subs += 1u << c.tshift;
+    bk.units = (bk.subs + c.g - 1) / c.g;
+  }
+  for (const BatchBlock& bk : p0) {
+    if ((bk.cls & 7u) != kClassTile0) continue;
+    BatchBlock b1 = bk;
+    b1.cls = (bk.cls & ~7u) | kClassTile1;
+    b1.unit0 = p1.empty() ? 0u : p1.back().unit0 + p1.back().units;
+    p1.push_back(b1);
+  }
+  if (p0.size() + p1.size() > (size_t)kMaxBlocks) return NTT_EINVAL_COUNT;   // not reachable: one block per class
+  *head = BatchHead{};
+  head->blocks[0] = (uint32_t)p0.size();
+  head->blocks[1] = (uint32_t)p1.size();
+  head->units[0] = p0.empty() ? 0u : p0.back().unit0 + p0.back().units;
+  head->units[1] = p1.empty() ? 0u : p1.back().unit0 + p1.back().units;
+  std::copy(p0.begin(), p0.end(), head->block);
+  std::copy(p1.begin(), p1.end(), head->block + p0.size());
+  *staged = n;
+  return NTT_OK;
+}
+
 ntt_status batch_prepare(ntt_batch* b, const ntt_batch_item* items, size_t count, size_t* out_count) {
   ntt_status st0 = wait_staging(b);
   if (st0) return st0;
@@ -274,6 +593,7 @@ ntt_status batch_prepare(ntt_batch* b, const ntt_batch_item* items, size_t count
                      return a.first > c.first;
                    });
   std::map<std::pair<uint64_t, uint64_t>, const ntt_plan*> seen;   // one cache lookup per distinct (N, q)
+  std::vector<BatchTask> list(count);
   for (size_t k = 0; k < count; ++k) {
     const ntt_batch_item& it = items[order[k].second];
     const ntt_plan*& p = seen[{it.N, it.q}];
@@ -281,7 +601,7 @@ ntt_status batch_prepare(ntt_batch* b, const ntt_batch_item* items, size_t count
       ntt_status st = cached_plan(it.N, it.q, &p);
       if (st) return st;
     }
-    BatchTask& t = staged_tasks(b)[k];
+    BatchTask& t = list[k];
     uint32_t op = 0, in_f = 1;
     (void)item_op(it, &op, &in_f);                 // validated above
     t.out = it.out;
@@ -292,9 +612,7 @@ ntt_status batch_prepare(ntt_batch* b, const ntt_batch_item* items, size_t count
     t.logN = (uint32_t)p->logN;
     t.op = op | batch_wide_flag(t.logN, it.q);
   }
-  *reinterpret_cast<uint32_t*>(cur_stage(b).host) = (uint32_t)count;
-  *out_count = count;
-  return NTT_OK;
+  return stage_units(b, list, out_count);
 }
 
 int batch_grid(const ntt_batch* b, size_t count) {
@@ -308,16 +626,18 @@ int batch_grid(const ntt_batch* b, size_t count) {
   return g < 1 ? 1 : g;
 }
 
-// Enqueues [descriptor copy of `staged` tasks, counter reset, persistent kernel] on `stream`.
-ntt_status batch_enqueue(ntt_batch* b, size_t staged, int grid, hipStream_t stream) {
+// Enqueues [descriptor copy of `staged` units, counter reset, phase 0, phase 1]
+// on `stream`; `phase1` false leaves out the second launch (nothing was split).
+ntt_status batch_enqueue(ntt_batch* b, size_t staged, int grid, hipStream_t stream, bool phase1) {
   ntt_batch_stage& g = cur_stage(b);
   if (hipMemcpyAsync(g.dev + kDevHead, g.host, stage_bytes(staged), hipMemcpyHostToDevice, stream) != hipSuccess)
     return NTT_EDEVICE;
   u32* counter = reinterpret_cast<u32*>(g.dev);
-  const u32* count = reinterpret_cast<const u32*>(g.dev + kDevHead);
+  const BatchHead* head = reinterpret_cast<const BatchHead*>(g.dev + kDevHead);
   const BatchTask* tasks = reinterpret_cast<const BatchTask*>(g.dev + kDevHead + kStageHead);
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, stream, counter);
-  hipLaunchKernelGGL(ntt_batch_kernel, dim3(grid), dim3(kBatchThreads), 0, stream, tasks, count, counter);
+  hipLaunchKernelGGL(ntt_batch_kernel, dim3(grid), dim3(kBatchThreads), 0, stream, tasks, head, counter, 0u);
+  if (phase1) hipLaunchKernelGGL(ntt_batch_kernel, dim3(grid), dim3(kBatchThreads), 0, stream, tasks, head, counter, 1u);
   return hipGetLastError() == hipSuccess ? NTT_OK : NTT_EDEVICE;
 }
 
@@ -325,19 +645,20 @@ static ntt_status batch_launch_staged(ntt_batch* b, size_t n, hipStream_t s, boo
   ntt_status st = NTT_OK;
   ntt_batch_stage& sg = cur_stage(b);
   if (!graph) {
-    st = batch_enqueue(b, n, batch_grid(b, n), s);
+    const BatchHead* head = reinterpret_cast<const BatchHead*>(sg.host);
+    st = batch_enqueue(b, n, batch_grid(b, std::max(head->units[0], head->units[1])), s, head->units[1] != 0);
     if (st) return st;
   } else {
     if (!sg.graph_exec) {
       // captured once per staging set with the full-capacity copy and grid; the kernel reads the count from device memory
-      const int grid = batch_grid(b, b->capacity);
+      const int grid = batch_grid(b, (size_t)1 << 30);
       hipStream_t cap = nullptr;
       if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return NTT_EDEVICE;
       if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipStreamDestroy(cap);
         return NTT_EDEVICE;
       }
-      st = batch_enqueue(b, b->capacity, grid, cap);
+      st = batch_enqueue(b, b->capacity, grid, cap, true);
       hipGraph_t g = nullptr;
       const hipError_t e = hipStreamEndCapture(cap, &g);
       (void)hipStreamDestroy(cap);
@@ -386,10 +707,12 @@ ntt_status batch_launch_tasks(ntt_batch* b, const BatchTask* tasks, size_t count
                    [](const std::pair<uint64_t, size_t>& a, const std::pair<uint64_t, size_t>& c) {
                      return a.first > c.first;
                    });
-  BatchTask* dst = staged_tasks(b);
-  for (size_t k = 0; k < count; ++k) dst[k] = tasks[order[k].second];
-  *reinterpret_cast<uint32_t*>(cur_stage(b).host) = (uint32_t)count;
-  return batch_launch_staged(b, count, stream, graph);
+  std::vector<BatchTask> list(count);
+  for (size_t k = 0; k < count; ++k) list[k] = tasks[order[k].second];
+  size_t n = 0;
+  st = stage_units(b, list, &n);
+  if (st) return st;
+  return batch_launch_staged(b, n, stream, graph);
 }
 
 }  // namespace nttamd
@@ -464,7 +787,7 @@ ntt_status ntt_batch_create(ntt_batch** out, size_t capacity) {
   for (ntt_batch_stage& g : b->stage) {
     ntt_status st = NTT_OK;
     if (hipHostMalloc((void**)&g.host, bytes, hipHostMallocDefault) != hipSuccess) { g.host = nullptr; st = NTT_ENOMEM; }
-    if (!st && hipMalloc((void**)&g.dev, kDevHead + bytes) != hipSuccess) { g.dev = nullptr; st = NTT_ENOMEM; }
+    if (!st && hipMalloc((void**)&g.dev, dev_bytes(b)) != hipSuccess) { g.dev = nullptr; st = NTT_ENOMEM; }
     if (!st && hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess) { g.done = nullptr; st = NTT_EDEVICE; }
     if (st) {
       for (ntt_batch_stage& h : b->stage) release_stage(h);

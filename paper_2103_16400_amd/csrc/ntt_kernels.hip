@@ -62,7 +62,7 @@ __global__ void __launch_bounds__((1 << (LOGT + LOGH + LOGC)) >> LOGR, MINW) ntt
   const u64 base = (u64)item << logN;
   tile_body<FWD, LOGT, LOGR, LOGC, LOGH, MODE, LASTPASS, PTOP, HAND>(pv, logN, a.b0, tile, a.in + base,
                                                                     a.out + base, a.mul ? a.mul + base : nullptr, lds,
-                                                                    true);
+                                                                    true, threadIdx.x, true);
 }
 
 // ---- schedules ---------------------------------------------------------------

@@ -195,18 +195,22 @@ __device__ __forceinline__ u64 unwiden(u64 v, const PlanView& pv) {
 }
 
 // Transforms one limb: reads `in` (N coefficients), writes `out`; the output
-// step applies MODE with the per-item multiplier / accumulator `mul`.
-template <bool FWD, int LOGN, int LOGR, bool SPLIT, int MODE, bool HAND = true, bool WIDE = false>
+// step applies MODE with the per-item multiplier / accumulator `mul`.  t is the
+// thread's index among the N / 2^LOGR threads that hold the limb; with active
+// false the threads run every step and barrier but store nothing (a sub-group
+// without a limb of its own, reading another's input).  FRESH: the twiddle and
+// output indices start from fresh views of t, so the compiler recomputes them
+// instead of keeping the input phase's (which spills inside a loop over limbs).
+template <bool FWD, int LOGN, int LOGR, bool SPLIT, int MODE, bool HAND = true, bool WIDE = false, bool FRESH = false>
 __device__ __forceinline__ void onchip_body(const PlanView& pv, const u64* in, u64* out, const u64* mul,
                                             typename OnChip<FWD, LOGN, LOGR, SPLIT, HAND, WIDE>::W* lds,
-                                            bool nt_load) {
+                                            bool nt_load, u32 t, bool active) {
   using K = OnChip<FWD, LOGN, LOGR, SPLIT, HAND, WIDE>;
   constexpr int R = K::R;
   constexpr int NT = K::NT;
   constexpr int RL = K::G::NR - 1;
   constexpr bool direct_in = K::G::lo(0) >= 4 || LOGN - LOGR < 4;
   constexpr bool direct_out = K::G::lo(RL) >= 4 || LOGN - LOGR < 4;
-  const u32 t = threadIdx.x;
   u64 x[R];
   if constexpr (direct_in) {
 #pragma unroll
@@ -224,7 +228,7 @@ __device__ __forceinline__ void onchip_body(const PlanView& pv, const u64* in, u
     K::shuffle(lds, x, [&](int j) { return K::lin_row(t, j); }, [&](int j) { return bi + K::template row_off<0>(j); });
   }
 
-  K::template run<0>(lds, x, t, pv);
+  K::template run<0>(lds, x, FRESH ? opaque(t) : t, pv);
   if constexpr (WIDE && FWD) {
     // before the output loop, so that its loads (fused multiply) can be grouped:
     // the compiler does not move memory accesses across these statements
@@ -232,13 +236,15 @@ __device__ __forceinline__ void onchip_body(const PlanView& pv, const u64* in, u
     for (int j = 0; j < R; ++j) x[j] = unwiden<true, true>(x[j], pv);
   }
 
+  const u32 to = FRESH ? opaque(t) : t;
   if constexpr (!direct_out) {
-    const u32 bo = K::template row_base<RL>(t);
-    K::shuffle(lds, x, [&](int j) { return bo + K::template row_off<RL>(j); }, [&](int j) { return K::lin_row(t, j); });
+    const u32 bo = K::template row_base<RL>(to);
+    K::shuffle(lds, x, [&](int j) { return bo + K::template row_off<RL>(j); }, [&](int j) { return K::lin_row(to, j); });
   }
+  if (!active) return;                            // past the last barrier: nothing left but the stores
 #pragma unroll
   for (int j = 0; j < R; ++j) {
-    const u32 i = direct_out ? K::template rho<RL>(t, j) : (u32)j * NT + t;
+    const u32 i = direct_out ? K::template rho<RL>(to, j) : (u32)j * NT + to;
     out[i] = finish_item<FWD, MODE>(FWD ? x[j] : unwiden<false, WIDE>(x[j], pv), mul, i, pv);
     if ((j & 7) == 7) stage_fence();
   }
@@ -254,11 +260,11 @@ __device__ __forceinline__ void onchip_body(const PlanView& pv, const u64* in, u
 // first LDS barrier, so out may equal m.  With WIDE, the forward's outputs are
 // first brought into [0, 3q), and the multiply leaves its remainder in [0, 3q)
 // (no final corrections), which the wide inverse accepts.
-template <int LOGN, int LOGR, bool SPLIT, int MODE, bool HAND = true, bool WIDE = false>
+template <int LOGN, int LOGR, bool SPLIT, int MODE, bool HAND = true, bool WIDE = false, bool FRESH = false>
 __device__ __forceinline__ void onchip_product_body(const PlanView& pf, const PlanView& pi, const u64* b,
                                                     const u64* m, u64* out,
                                                     typename OnChip<true, LOGN, LOGR, SPLIT, HAND, WIDE>::W* lds,
-                                                    bool nt_load) {
+                                                    bool nt_load, u32 t, bool active) {
   // The forward half names its block size explicitly: the same three pairs as the
   // rule gives, but as its own instantiation the compiler schedules the fused
   // kernel's registers better (measured 0.829 against 0.865 ms at N = 2^14 x 4096).
@@ -271,7 +277,6 @@ __device__ __forceinline__ void onchip_product_body(const PlanView& pf, const Pl
   static_assert(KF::G::lo(RLF) == 0 && KI::G::lo(0) == 0, "forward output and inverse input layouts must coincide");
   constexpr bool direct_in = KF::G::lo(0) >= 4 || LOGN - LOGR < 4;
   constexpr bool direct_out = KI::G::lo(RLI) >= 4 || LOGN - LOGR < 4;
-  const u32 t = threadIdx.x;
   u64 x[R];
   if constexpr (direct_in) {
 #pragma unroll
@@ -288,7 +293,7 @@ __device__ __forceinline__ void onchip_product_body(const PlanView& pf, const Pl
     const u32 bi = KF::template row_base<0>(t);
     KF::shuffle(lds, x, [&](int j) { return KF::lin_row(t, j); }, [&](int j) { return bi + KF::template row_off<0>(j); });
   }
-  KF::template run<0>(lds, x, t, pf);
+  KF::template run<0>(lds, x, FRESH ? opaque(t) : t, pf);
   if constexpr (WIDE) {
     // all reductions first: the compiler does not move the multiplier loads across
     // these statements, and grouped loads hide their latency
@@ -309,6 +314,7 @@ __device__ __forceinline__ void onchip_product_body(const PlanView& pf, const Pl
     const u32 bo = KI::template row_base<RLI>(to);
     KI::shuffle(lds, x, [&](int j) { return bo + KI::template row_off<RLI>(j); }, [&](int j) { return KI::lin_row(to, j); });
   }
+  if (!active) return;
 #pragma unroll
   for (int j = 0; j < R; ++j) {
     const u32 i = direct_out ? KI::template rho<RLI>(to, j) : (u32)j * NT + to;

@@ -37,7 +37,8 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR), MINW) ntt_onchip_kernel(co
   const u32 item = a.item0 + blockIdx.x;
   const PlanView pv = load_plan(a.plan[item % a.num_limbs], FWD, (u64)K::N);
   const u64 base = (u64)item << LOGN;
-  onchip_body<FWD, LOGN, LOGR, SPLIT, MODE, true, WIDE>(pv, a.in + base, a.out + base, a.mul ? a.mul + base : nullptr, lds, true);
+  onchip_body<FWD, LOGN, LOGR, SPLIT, MODE, true, WIDE>(pv, a.in + base, a.out + base, a.mul ? a.mul + base : nullptr, lds, true,
+                                                     threadIdx.x, true);
 }
 
 // Fused negacyclic product per limb: in = b, mul = NTT(a) (lazy), out =
@@ -51,7 +52,8 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR), MINW) ntt_onchip_product_k
   const PlanView pf = load_plan(plan, true, (u64)K::N);
   const PlanView pi = load_plan(plan, false, (u64)K::N);
   const u64 base = (u64)item << LOGN;
-  onchip_product_body<LOGN, LOGR, SPLIT, MODE, true, WIDE>(pf, pi, a.in + base, a.mul + base, a.out + base, lds, true);
+  onchip_product_body<LOGN, LOGR, SPLIT, MODE, true, WIDE>(pf, pi, a.in + base, a.mul + base, a.out + base, lds, true,
+                                                      threadIdx.x, true);
 }
 
 typedef void (*OnchipKernel)(const PassArgs);

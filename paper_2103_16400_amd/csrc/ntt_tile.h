@@ -143,10 +143,13 @@ struct TileNtt {
 };
 
 // Runs one tile of one pass.  in/out/mul point at the limb's first coefficient;
-// `tile` selects the tile inside the limb; b0 = lowest index bit of the pass.
+// `tile` selects the tile inside the limb; b0 = lowest index bit of the pass;
+// t = the thread's index among the tile's threads; with active false nothing is
+// stored.
 template <bool FWD, int LOGT, int LOGR, int LOGC, int LOGH, int MODE, bool LASTPASS, int PTOP, bool HAND = true>
 __device__ __forceinline__ void tile_body(const PlanView& pv, u32 logN, u32 b0, u32 tile, const u64* in_item,
-                                          u64* out_item, const u64* mul, u64* lds, bool nt_load) {
+                                          u64* out_item, const u64* mul, u64* lds, bool nt_load, u32 t,
+                                          bool active) {
   using K = TileNtt<FWD, LOGT, LOGR, LOGC, LOGH, HAND>;
   constexpr int R = K::R;
   constexpr int C = K::C;
@@ -163,7 +166,6 @@ __device__ __forceinline__ void tile_body(const PlanView& pv, u32 logN, u32 b0, 
   } else {
     g_tile = (u64)tile << (LOGT + LOGH);
   }
-  const u32 t = threadIdx.x;
   const u32 c = t & (C - 1);
   const u32 o = t >> LOGC;
   const u64* in = in_item + g_tile;
@@ -192,6 +194,7 @@ __device__ __forceinline__ void tile_body(const PlanView& pv, u32 logN, u32 b0, 
     const u32 bo = K::template row_base<RL>(o);
     K::shuffle(lds, x, 0, [&](int j) { return bo + K::template row_off<RL>(j); }, [&](int j) { return K::lin_row(t, j); });
   }
+  if (!active) return;                            // past the last barrier: nothing left but the stores
 #pragma unroll
   for (int j = 0; j < R; ++j) {
     const u64 i = direct_out ? (((u64)K::template rho<RL>(o, j) << b0) + c) : (u64)((u32)j * NT + t);
