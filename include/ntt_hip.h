@@ -350,8 +350,10 @@ ntt_status poly_mul_acc_ntt_rns32(uint32_t* acc, const uint32_t* a_ntt, const ui
 /* ---------------------------------------------------------------------------
  * Batches of limb tasks with uneven ring degrees in one persistent launch.
  * RNS polynomials of different sizes and limb counts (Section 5) are lists of
- * independent limb transforms; a batch runs any mix of them in one kernel
- * launch (workgroups claim tasks from a device-side counter, largest first).
+ * independent limb transforms; a batch runs any mix of them in one persistent
+ * kernel launch (workgroups claim units of work from a device-side counter),
+ * plus a second launch for the last pass when the batch holds transforms with
+ * N >= 2^15.
  *
  * ntt_batch_item: one limb task, N in [2^10, 2^17], q its modulus (plans come
  *   from the library cache, smallest psi), device pointers to N words each:
