@@ -431,14 +431,17 @@ ntt_status ntt_batch_autotune(ntt_batch* batch, const ntt_batch_item* items, siz
 /* ---------------------------------------------------------------------------
  * Autotuning (Section 4 notes that the best implementation can be picked by
  * trying the candidates at initialisation).  For two-pass sizes (N > 2^14) the
- * library has several kernel variants per pass; this call times each, 20
+ * library has several kernel variants per pass (thread shapes and N1 x N2
+ * splits), for N = 2^10 .. 2^14 two thread shapes of the single-pass kernel
+ * (variant 1 gives each limb twice the threads); this call times each, 20
  * launches per variant, on scratch operand sets of num_limbs * num_polys * N
  * words used in turn (enough sets, up to 32, that they exceed the 256 MB MALL,
  * so the data comes from HBM as in a streaming workload; allocated and freed
  * here, so it is not a hot-path call), synchronises `stream`, and uses the
  * fastest for later calls of the same direction, N and batch-size class (up to
  * 64 limbs, or more).  choice_fwd / choice_inv (may be NULL)
- * receive the chosen variant indices.  N <= 2^14 has a single variant.
+ * receive the chosen variant indices.  N < 2^10 has a single variant; the
+ * fused products (poly_mul_*) always take the single-pass kernel's variant 0.
  * ntt_set_variant pins a variant explicitly (forward != 0 for the forward
  * transform); NTT_EINVAL_COUNT for an unknown variant.
  */

@@ -659,7 +659,7 @@ ntt_status ntt_autotune(uint64_t N, const uint64_t* moduli, uint64_t num_limbs, 
   const int logN = plans[0]->logN;
   const uint64_t items = num_limbs * num_polys;
   int best[2] = {0, 0};
-  if (pass_count(logN) > 1) {
+  if (variant_count(logN) > 1) {
     // Scratch on the device for timing only (not a hot-path call): enough distinct operand
     // sets, used in turn, that the working set exceeds the 256 MB MALL as it does in a
     // streaming workload, so each variant is timed on data coming from HBM.
@@ -684,7 +684,7 @@ ntt_status ntt_autotune(uint64_t N, const uint64_t* moduli, uint64_t num_limbs, 
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
     const int reps = 20;
-    const int nv = hi_variant_count();
+    const int nv = variant_count(logN);
     auto run = [&](int dir, int v, int r) {
       uint64_t* x = buf + (size_t)(r % rot) * (bytes / sizeof(uint64_t));
       // operands below q, transformed in place: every value stays within the input
@@ -733,8 +733,8 @@ ntt_status ntt_set_variant(uint64_t N, uint64_t num_items, int forward, int vari
   if (st) return st;
   int logN = 0;
   while ((1ull << logN) < N) ++logN;
-  if (variant < 0 || variant >= hi_variant_count()) return NTT_EINVAL_COUNT;
-  if (pass_count(logN) > 1) set_hi_variant(forward != 0, logN, num_items, variant);
+  if (variant < 0 || variant >= variant_count(logN)) return NTT_EINVAL_COUNT;
+  if (variant_count(logN) > 1) set_hi_variant(forward != 0, logN, num_items, variant);
   return NTT_OK;
 }
 

@@ -129,11 +129,13 @@ ntt_status launch_forward(const NttLaunch& l);
 // mul_into is NTT(a) with the forward's lazy output range; out may equal mul_into.
 ntt_status launch_product(const NttLaunch& l, bool acc);
 int pass_count(int logN);
-// autotuner hooks (ntt_kernels.hip): variants of the high pass of two-pass transforms
+// autotuner hooks (ntt_kernels.hip): schedule variants of the transforms (the
+// thread shapes and splits of the two-pass sizes, two thread shapes of the
+// single-pass sizes 2^10 .. 2^14)
 ntt_status launch_variant(const NttLaunch& l, bool fwd, int variant);
 void set_hi_variant(bool fwd, int logN, uint64_t items, int variant);
 int get_hi_variant(bool fwd, int logN, uint64_t items);
-int hi_variant_count();
+int variant_count(int logN);
 ntt_status launch_inverse(const NttLaunch& l);
 
 struct EltLaunch {

@@ -115,7 +115,9 @@ __device__ __forceinline__ u64 finish(u64 v, u64 idx, const PassArgs& a, const P
 
 // wide: use the wide-range butterflies; valid when every modulus of the launch
 // is below kWideModulusBound.
-ntt_status launch_onchip(const PassArgs& base_args, uint64_t items, bool fwd, bool wide, hipStream_t stream);
+// variant 0: 2^onchip_logr(logN) coefficients per thread; 1 (N = 2^10 .. 2^14): half as many
+ntt_status launch_onchip(const PassArgs& base_args, uint64_t items, bool fwd, bool wide, hipStream_t stream,
+                         int variant);
 // Fused product per limb for N <= 2^14: in = b, mul = NTT(a) lazy, out =
 // canonical product (acc false) or accumulator += product (acc true).
 ntt_status launch_onchip_product(const PassArgs& base_args, uint64_t items, bool acc, bool wide,

@@ -173,7 +173,7 @@ void set_hi_variant(bool fwd, int logN, uint64_t items, int variant) {
 int get_hi_variant(bool fwd, int logN, uint64_t items) {
   return g_hi_variant[variant_device()][fwd ? 1 : 0][logN][batch_bucket(items)].load(std::memory_order_relaxed);
 }
-int hi_variant_count() { return kVariants; }
+int variant_count(int logN) { return logN > kMaxOnchipLog ? kVariants : (logN >= 10 ? 2 : 1); }
 
 static std::atomic<int> g_wide_range{1};
 bool wide_range_enabled() { return g_wide_range.load(std::memory_order_relaxed) != 0; }
@@ -208,7 +208,9 @@ static ntt_status launch_passes(const NttLaunch& l, bool fwd, int force_variant)
     a.out = l.out;
     a.b0 = 0;
     a.flags = last_flags;
-    ntt_status st = launch_onchip(a, items, fwd, use_wide(l), l.stream);
+    const int variant = force_variant >= 0 ? force_variant : get_hi_variant(fwd, logN, items);
+    if (variant < 0 || variant >= variant_count(logN)) return NTT_EINVAL_COUNT;
+    ntt_status st = launch_onchip(a, items, fwd, use_wide(l), l.stream, variant);
     if (st) return st;
     return hipGetLastError() == hipSuccess ? NTT_OK : NTT_EDEVICE;
   }

@@ -58,8 +58,27 @@ __global__ void __launch_bounds__(1 << (LOGN - LOGR), MINW) ntt_onchip_product_k
 
 typedef void (*OnchipKernel)(const PassArgs);
 
+// Variant 1 (N = 2^10 .. 2^14): half the coefficients per thread of variant 0,
+// so twice the threads per limb: more waves hide latency when few limbs are in
+// flight, at the price of one more LDS round and the natural twiddle table in
+// every round (the transposed sub-tables are laid out for variant 0's shape).
 template <bool FWD, int MODE, bool WIDE>
-static OnchipKernel pick_onchip_mode(int logN) {
+static OnchipKernel pick_onchip_mode_v1(int logN) {
+  switch (logN) {
+    case 10: return ntt_onchip_kernel<FWD, 10, 3, false, 8, MODE, WIDE>;
+    case 11: return ntt_onchip_kernel<FWD, 11, 3, false, 8, MODE, WIDE>;
+    case 12: return ntt_onchip_kernel<FWD, 12, 3, false, 8, MODE, WIDE>;
+    case 13: return ntt_onchip_kernel<FWD, 13, 4, true, 4, MODE, WIDE>;
+    case 14: return ntt_onchip_kernel<FWD, 14, 4, true, 4, MODE, WIDE>;
+    default: return nullptr;
+  }
+}
+static int onchip_logr_variant(int logN, int variant) { return onchip_logr(logN) - (variant == 1 ? 1 : 0); }
+
+template <bool FWD, int MODE, bool WIDE>
+static OnchipKernel pick_onchip_mode(int logN, int variant) {
+  if (variant == 1) return pick_onchip_mode_v1<FWD, MODE, WIDE>(logN);
+  if (variant != 0) return nullptr;
   switch (logN) {
     case 1: return ntt_onchip_kernel<FWD, 1, onchip_logr(1), false, 1, MODE, WIDE>;
     case 2: return ntt_onchip_kernel<FWD, 2, onchip_logr(2), false, 1, MODE, WIDE>;
@@ -80,19 +99,19 @@ static OnchipKernel pick_onchip_mode(int logN) {
 }
 
 template <bool WIDE>
-static OnchipKernel pick_onchip_w(bool fwd, int logN, u32 flags) {
+static OnchipKernel pick_onchip_w(bool fwd, int logN, u32 flags, int v) {
   if (fwd) {
-    if (flags & kFlagMul) return pick_onchip_mode<true, kOutMul, WIDE>(logN);
-    if (flags & kFlagCanon) return pick_onchip_mode<true, kOutCanon, WIDE>(logN);
-    return pick_onchip_mode<true, kOutLazy, WIDE>(logN);
+    if (flags & kFlagMul) return pick_onchip_mode<true, kOutMul, WIDE>(logN, v);
+    if (flags & kFlagCanon) return pick_onchip_mode<true, kOutCanon, WIDE>(logN, v);
+    return pick_onchip_mode<true, kOutLazy, WIDE>(logN, v);
   }
-  if (flags & kFlagAcc) return pick_onchip_mode<false, kOutAcc, WIDE>(logN);
-  if (flags & kFlagCanon) return pick_onchip_mode<false, kOutCanon, WIDE>(logN);
-  return pick_onchip_mode<false, kOutLazy, WIDE>(logN);
+  if (flags & kFlagAcc) return pick_onchip_mode<false, kOutAcc, WIDE>(logN, v);
+  if (flags & kFlagCanon) return pick_onchip_mode<false, kOutCanon, WIDE>(logN, v);
+  return pick_onchip_mode<false, kOutLazy, WIDE>(logN, v);
 }
 
-static OnchipKernel pick_onchip(bool fwd, int logN, u32 flags, bool wide) {
-  return wide ? pick_onchip_w<true>(fwd, logN, flags) : pick_onchip_w<false>(fwd, logN, flags);
+static OnchipKernel pick_onchip(bool fwd, int logN, u32 flags, bool wide, int v) {
+  return wide ? pick_onchip_w<true>(fwd, logN, flags, v) : pick_onchip_w<false>(fwd, logN, flags, v);
 }
 
 template <int MODE, bool WIDE>
@@ -131,16 +150,17 @@ ntt_status launch_onchip_product(const PassArgs& base_args, uint64_t items, bool
   return hipGetLastError() == hipSuccess ? NTT_OK : NTT_EDEVICE;
 }
 
-ntt_status launch_onchip(const PassArgs& base_args, uint64_t items, bool fwd, bool wide, hipStream_t stream) {
+ntt_status launch_onchip(const PassArgs& base_args, uint64_t items, bool fwd, bool wide, hipStream_t stream,
+                         int variant) {
   const int logN = (int)base_args.logN;
-  OnchipKernel k = pick_onchip(fwd, logN, base_args.flags, wide);
+  OnchipKernel k = pick_onchip(fwd, logN, base_args.flags, wide, variant);
   if (!k) return NTT_EINVAL_DEGREE;
   PassArgs a = base_args;
   const uint64_t kMaxX = 1u << 30;
   for (uint64_t it0 = 0; it0 < items; it0 += kMaxX) {
     const uint64_t nx = (items - it0) < kMaxX ? (items - it0) : kMaxX;
     a.item0 = (u32)it0;
-    hipLaunchKernelGGL(k, dim3((unsigned)nx), dim3(1 << (logN - onchip_logr(logN))), 0, stream, a);
+    hipLaunchKernelGGL(k, dim3((unsigned)nx), dim3(1 << (logN - onchip_logr_variant(logN, variant))), 0, stream, a);
   }
   return NTT_OK;
 }

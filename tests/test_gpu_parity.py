@@ -399,6 +399,65 @@ def test_two_pass_schedule_variants(nt, logN):
         nt.set_variant(N, L, False, 0)
 
 
+@pytest.mark.parametrize("logN", [10, 11, 12, 13, 14])
+def test_single_pass_variants(nt, logN):
+    """Both thread shapes of the single-pass kernel (variant 1: half the coefficients per thread)
+    give the oracle's words in every output mode, with the paper's butterflies (a modulus of 60
+    bits in the launch) and with the wide-range ones (every modulus below 2^58)."""
+    N = 1 << logN
+    serving = PRIMES["serving"]["moduli"]
+    assert _variant_count(nt, N) == 2
+    B = 3
+    for moduli in ([serving[2], serving[10]], [serving[0], serving[7]]):
+        L = len(moduli)
+        items = B * L
+        psis = [oracle.min_root(N, q) for q in moduli]
+        a = _rns_inputs(86, N, moduli, B, 4)
+        A = _rns_inputs(87, N, moduli, B, 2)
+        m = _rns_inputs(88, N, moduli, B, 4)
+        acc0 = _rns_inputs(89, N, moduli, B, 1)
+        lim = [(p * L + l, moduli[l], psis[l]) for p in range(B) for l in range(L)]
+        sl = lambda i: slice(i * N, (i + 1) * N)
+        harvey = [oracle.harvey_forward(a[sl(i)], q, psi, 4) for i, q, psi in lim]
+        fwd_c = [oracle.harvey_forward(a[sl(i)], q, psi, 1) for i, q, psi in lim]
+        inv_c = [oracle.harvey_inverse(A[sl(i)], q, psi, 1) for i, q, psi in lim]
+        exact = lazy_words_exact(nt, N, moduli)
+        ws = empty_dev(items * N)
+        try:
+            for v in (0, 1):
+                nt.set_variant(N, items, True, v)
+                nt.set_variant(N, items, False, v)
+                da, dout = to_dev(a), empty_dev(items * N)
+                nt.ntt_forward_rns(dout, da, N, moduli, B, 4, 4)
+                lazy = from_dev(dout)
+                nt.ntt_forward_rns(dout, da, N, moduli, B, 4, 1)
+                canon = from_dev(dout)
+                dm = to_dev(m)
+                nt.ntt_forward_mul_rns(dm, da, dm, N, moduli, B, 4, ws)
+                prod = from_dev(dm)
+                dA = to_dev(A)
+                nt.ntt_inverse_rns(dout, dA, N, moduli, B, 2, 1)
+                inv = from_dev(dout)
+                nt.ntt_inverse_rns(dout, dA, N, moduli, B, 2, 2)
+                inv_lazy = from_dev(dout)
+                dacc = to_dev(acc0)
+                nt.ntt_inverse_acc_rns(dacc, dA, N, moduli, B, 2, ws)
+                acc = from_dev(dacc)
+                for k, (i, q, psi) in enumerate(lim):
+                    s, qq = sl(i), np.uint64(q)
+                    assert np.all(lazy[s] < 4 * qq) and np.array_equal(lazy[s] % qq, fwd_c[k]), (v, i)
+                    if exact:
+                        assert np.array_equal(lazy[s], harvey[k]), (v, i)
+                    assert np.array_equal(canon[s], fwd_c[k]), (v, i)
+                    assert np.array_equal(prod[s], oracle.eltwise_mult(fwd_c[k], m[s], q)), (v, i)
+                    assert np.array_equal(inv[s], inv_c[k]), (v, i)
+                    assert np.all(inv_lazy[s] < 2 * qq) and np.array_equal(inv_lazy[s] % qq, inv_c[k]), (v, i)
+                    assert np.array_equal(acc[s], oracle.eltwise_add(acc0[s], inv_c[k], q)), (v, i)
+        finally:
+            nt.set_variant(N, items, True, 0)
+            nt.set_variant(N, items, False, 0)
+
+
 @pytest.mark.parametrize("key,B", [("rns_16384", 2), ("large_65536", 1)])
 def test_rns_forward_inverse(nt, key, B):
     N = PRIMES[key]["N"]
@@ -686,6 +745,31 @@ def test_batch_uneven_mixed_ops(nt):
                 assert np.array_equal(from_dev(ref), from_dev(out)), (wide, op, N)
     finally:
         nt.set_wide_range(True)
+    batch.close()
+
+
+def test_batch_partial_units_in_place(nt):
+    """Blocks whose last unit is partial (N <= 2^14 runs 8, 4, 2, 2, 1 limbs per workgroup; the
+    spare sub-groups repeat the unit's first limb and store nothing), half of the transforms in
+    place (out = in, which the spare sub-groups read while the first limb is written), and tile
+    pairs of the two-pass sizes with an odd number of limbs: every output against the oracle."""
+    serving = PRIMES["serving"]["moduli"]
+    per_unit = {10: 8, 11: 4, 12: 2, 13: 2, 14: 1}
+    specs = []
+    for logN, g in per_unit.items():
+        for op in (nt.BATCH_FWD_LAZY, nt.BATCH_INV, nt.BATCH_PRODUCT):
+            specs += [(op, logN, serving[(logN + j) % len(serving)]) for j in range(2 * g + max(1, g - 1))]
+    for logN in (15, 16):
+        specs += [(nt.BATCH_FWD, logN, serving[j % len(serving)]) for j in range(3)]
+        specs += [(nt.BATCH_INV_LAZY, logN, serving[(j + 5) % len(serving)]) for j in range(3)]
+    tasks, host = _batch_case(nt, 140, specs)
+    # every other transform in place
+    for k, t in enumerate(tasks):
+        if t[0] != nt.BATCH_PRODUCT and k % 2 == 0:
+            tasks[k] = (t[0], t[2], t[2], t[3], t[4], t[5], t[6])
+    batch = nt.Batch(len(tasks))
+    batch.run(tasks)
+    _check_batch_outputs(nt, tasks, host)
     batch.close()
 
 
