@@ -46,10 +46,10 @@ HBM_PEAK_GBS = 8000.0
 # Valid only for the kernel sources they were taken with, identified by the SHA-256 of these files.
 COUNTERS_N16384 = {
     "sources": ["ntt_onchip.hip", "ntt_onchip.h", "ntt_common.h", "modarith.h", "internal.h", "ntt_kernels.hip"],
-    "sha256": "0ceb77bf00d3592247e1e895bb73db07beb04f8414502adff5ee37a03dd4ccc0",
+    "sha256": "3b84549f7622a01fef57a0bee9836c8d71eb4613535b90e8ab166d97960c8a3c",
     "fetch_scale": 2.0, "write_scale": 1.0,
-    "product": {"fetch_kib": 887933.6, "write_kib": 540672.0, "valu_insts": 394428416},
-    "forward": {"fetch_kib": 290376.7, "write_kib": 573440.3, "valu_insts": 145096704},
+    "product": {"fetch_kib": 886963.8, "write_kib": 540672.0, "valu_insts": 394428416},
+    "forward": {"fetch_kib": 294642.5, "write_kib": 581632.0, "valu_insts": 145195008},
 }
 
 # VALU issue capacity: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at 2.4 GHz
