@@ -154,7 +154,7 @@ ntt_status launch_eltwise_mult(const EltLaunch& l);
 ntt_status launch_eltwise_sub(const EltLaunch& l, bool negate);   // b unused when negating
 ntt_status launch_eltwise_fma(const EltLaunch& l);                // b = addend or nullptr
 // Persistent batch launch of already-resolved tasks (ntt_batch.hip); sorts them
-// largest first into the context's staging buffer.
+// into class blocks in the context's staging buffer.
 ntt_status batch_launch_tasks(ntt_batch* b, const BatchTask* tasks, size_t count, hipStream_t stream, bool graph);
 ntt_status launch_eltwise_add(const EltLaunch& l);
 
