@@ -236,6 +236,40 @@ def time_uneven_batch(nt, torch, primes, reps=10):
     return res
 
 
+def time_batch_one_size(nt, torch, primes, logN, polys=320, reps=10):
+    """5120 limbs of one ring degree (320 polynomials x the 16 primes of the uneven pool), forward
+    1 -> 4: the persistent batch (plain launches, grid of two workgroups per CU) against one
+    `ntt_forward_rns` launch over the same limbs.  Event-timed calls include the host's
+    preparation of each batch; a kernel trace of this mode gives the kernels' own durations."""
+    from synthetic import uniform_mod, unit_seed
+    pool = primes["uneven"]["moduli"][:16]
+    N, L = 1 << logN, len(pool)
+    dev = torch.device("cuda:0")
+    host = np.concatenate([uniform_mod(unit_seed(7, p, l), N, pool[l]) for p in range(polys) for l in range(L)])
+    src = torch.from_numpy(host.view(np.int64)).to(dev)
+    dst = torch.empty_like(src)
+    items, cnt = nt.Batch.make_items([(nt.BATCH_FWD_LAZY, dst[k * N:(k + 1) * N], src[k * N:(k + 1) * N], None,
+                                       None, N, pool[k % L]) for k in range(polys * L)])
+    batch = nt.Batch(polys * L)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return round(e0.elapsed_time(e1) * 1e3 / reps, 1)
+    res = {"logN": logN, "limbs": polys * L,
+           "batch_us": timed(lambda: batch.run(items, cnt, stream=stream)),
+           "rns_us": timed(lambda: nt.ntt_forward_rns(dst, src, N, pool, polys, 1, 4, stream=stream))}
+    batch.close()
+    return res
+
+
 SERVE_RATES = (1000, 2000, 5000, 10000, 20000, 30000, 40000, 50000)
 
 
@@ -525,6 +559,8 @@ def main():
                          "(for profiling the two-pass kernels)")
     ap.add_argument("--uneven-only", action="store_true",
                     help="only time the uneven batch (256 polynomials, N in 2^12..2^15) as one persistent launch")
+    ap.add_argument("--batch-one-size", type=int, default=0, metavar="LOGN",
+                    help="only time a batch of 5120 limbs of N = 2^LOGN against the per-size kernels")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 4 times (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -553,6 +589,11 @@ def main():
 
     if args.uneven_only:
         print(json.dumps({"uneven_batch_256polys": time_uneven_batch(nt, torch, load_primes())}), flush=True)
+        return
+
+    if args.batch_one_size:
+        print(json.dumps({"batch_one_size": time_batch_one_size(nt, torch, load_primes(), args.batch_one_size)}),
+              flush=True)
         return
 
     if args.serve_only:
