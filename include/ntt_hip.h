@@ -383,10 +383,11 @@ ntt_status poly_mul_acc_ntt_rns32(uint32_t* acc, const uint32_t* a_ntt, const ui
  *   launched).
  * ntt_batch_run_graph: same work through a hipGraph (one per staging set)
  *   captured on first use:
- *   [descriptor copy, counter reset, persistent kernel]; the graph reads the
- *   task list and count from device memory, so it is replayed for every later
- *   batch of up to `capacity` tasks, its copy resized to the batch's own
- *   descriptors before each replay.
+ *   [persistent kernel, second launch for the last passes]; the graph reads
+ *   the task list and counts from device memory, so it is replayed for every
+ *   later batch of up to `capacity` tasks.  Each run (plain or graph) first
+ *   copies its own descriptors on a stream of the context, ordered before the
+ *   kernels by an event.
  * ntt_batch_set_grid: number of persistent workgroups (0 = two per CU).
  */
 typedef struct ntt_batch ntt_batch;

@@ -18,11 +18,13 @@
 //     one workgroup runs all three two-pass transforms.
 // Forward outputs are lazy [0, 4q) or canonical, inverse outputs lazy [0, 2q)
 // or canonical.  The blocks, the descriptors and their counts live in device
-// memory, so a captured graph of [descriptor copy, counter reset, phase 0,
-// phase 1] can be replayed for any batch.
+// memory, so a captured graph of [descriptor copy, phase 0, phase 1] can be
+// replayed for any batch; each phase's claim counter is cleared by the
+// workgroup that makes the phase's last claim.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -37,19 +39,20 @@
 // Two staging sets are used in turn, so the host can prepare the next batch
 // while the previous one still runs.
 struct ntt_batch_stage {
-  unsigned char* host;             // pinned staging: count word (128-byte line), then the tasks
-  unsigned char* dev;              // device: claim counter (own line), count word, tasks
+  unsigned char* host;             // pinned staging: the head (blocks and counts), then the tasks
+  unsigned char* dev;              // device: claim counters (own line), then the staging's copy
   hipEvent_t done;                 // completion of the last run from this set
+  hipEvent_t copied;               // plain runs: the descriptor copy on the context's copy stream
   bool pending;
   hipGraph_t graph;
-  hipGraphExec_t graph_exec;
-  hipGraphNode_t copy_node;        // the graph's descriptor copy, resized before each replay
+  hipGraphExec_t graph_exec;       // [phase 0, phase 1]; the descriptor copy runs before each replay
 };
 struct ntt_batch {
   int device;
   size_t capacity;                 // tasks
   int grid;                        // persistent workgroups (0: automatic)
   int cur;                         // staging set of the next run
+  hipStream_t copy_stream;         // plain runs copy their descriptors here, overlapping the previous run
   ntt_batch_stage stage[2];
 };
 
@@ -61,7 +64,9 @@ enum : uint32_t { kClassOnchip = 0, kClassProduct = 1, kClassTile0 = 2, kClassTi
 struct BatchBlock {
   uint32_t unit0, units;    // claim indices [unit0, unit0 + units) of the phase
   uint32_t desc0, subs;     // first descriptor; sub-tasks (limbs, or tiles: N / 4096 per descriptor)
-  uint32_t cls, pad[3];
+  uint32_t cls;
+  uint32_t last;            // set on the device: the phase's last claim value (its workgroup clears the counter)
+  uint32_t pad[2];
 };
 // Every class present in a batch has one block per phase it runs in: at most
 // 40 single-pass transform classes, 13 product classes and 12 two-pass
@@ -164,7 +169,7 @@ __device__ __forceinline__ PlanView load_plan_batch(const u64* plan, bool fwd, u
 template <typename F>
 __device__ __forceinline__ u32 run_block(const BatchBlock& bk_in, u32* ctr_in, u32* claimed_in, u32 u, u32 g, F&& body) {
   const u32 unit0 = rfl(bk_in.unit0), units = rfl(bk_in.units);
-  const u32 subs = rfl(bk_in.subs);
+  const u32 subs = rfl(bk_in.subs), last = rfl(bk_in.last);
   u32* ctr = uniform_ptr(ctr_in);
   u32* claimed = uniform_ptr(claimed_in);
   const u32 nt = kBatchThreads / g;             // a multiple of the wave size
@@ -180,7 +185,10 @@ __device__ __forceinline__ u32 run_block(const BatchBlock& bk_in, u32* ctr_in, u
     // inside the unit rather than held in registers across the loop
     body(active ? k0 + h : k0, opaque(t), active, h);
     __syncthreads();                            // LDS reuse, and every thread has read `claimed`
-    if (threadIdx.x == 0) *claimed = next;
+    if (threadIdx.x == 0) {
+      *claimed = next;
+      if (next == last) __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __syncthreads();
     u = rfl(*claimed);
     if (u - unit0 >= units) return u;
@@ -388,12 +396,6 @@ __device__ __forceinline__ u32 run_class(const BatchTask* tasks, const BatchBloc
   }
 }
 
-// Clears the two claim counters (a kernel, not a memset, so that a captured
-// graph replays it faithfully).
-__global__ void batch_reset_kernel(u32* counter) {
-  if (threadIdx.x < 2) counter[threadIdx.x] = 0;
-}
-
 // One phase of a batch.  Phase 0 runs the whole tasks and the first pass of
 // every split two-pass transform, phase 1 the last passes: the launch boundary
 // orders the two passes of a split transform, so no workgroup waits on another.
@@ -406,7 +408,14 @@ __global__ void __launch_bounds__(kBatchThreads, 4)
   const u32 b_first = phase ? head->blocks[0] : 0u;
   const u32 b_end = b_first + head->blocks[phase];
   u32* ctr = counter + phase;
-  if (threadIdx.x == 0) claimed = atomicAdd(ctr, 1u);
+  // Every workgroup makes exactly one claim past the phase's units, so the claim
+  // values end at units + grid - 1; the workgroup that draws that value has seen
+  // every claim of the launch performed and clears the counter for the next run.
+  const u32 last = head->units[phase] + gridDim.x - 1u;
+  if (threadIdx.x == 0) {
+    claimed = atomicAdd(ctr, 1u);
+    if (claimed == last) __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   __syncthreads();
   u32 u = rfl(claimed);
   u32 b = b_first;
@@ -414,17 +423,13 @@ __global__ void __launch_bounds__(kBatchThreads, 4)
   for (;;) {
     while (b < b_end && u - head->block[b].unit0 >= head->block[b].units) ++b;
     if (b >= b_end) break;                      // every wave of every workgroup reaches this exit
-    const BatchBlock bk = head->block[b];
+    BatchBlock bk = head->block[b];
+    bk.last = last;
     u = run_class(tasks, bk, ctr, &claimed, u, lds);
   }
 }
 
 // ---- host side ----------------------------------------------------------------
-
-static uint64_t task_cost(uint32_t logN, uint32_t op) {
-  const uint64_t n = 1ull << logN;
-  return n * logN * ((op & kBatchOpMask) == kBatchProduct ? 3 : 1);
-}
 
 uint32_t batch_wide_flag(uint32_t logN, uint64_t q) {
   return (wide_range_enabled() && logN <= (uint32_t)kMaxOnchipLog && q < kWideModulusBound) ? kBatchWide : 0u;
@@ -506,19 +511,85 @@ static TaskClass classify(const BatchTask& t) {
 // twiddle tables in L2.  Two-pass transforms (N >= 2^15, not products) run as
 // tiles: the first pass in phase 0, the last pass in phase 1 (same
 // descriptors).  *staged = the number of descriptors.
+// Groups of tasks of one (class, plan): found through a small open-addressing
+// table, so that ordering a batch costs O(tasks) plus a sort of the groups.
+struct TaskGroup {
+  uint64_t cost;
+  uint32_t cls;
+  const uint64_t* plan;
+  uint32_t count, next;
+};
+class GroupTable {
+ public:
+  explicit GroupTable(size_t expect) {
+    size_t cap = 64;
+    while (cap < 2 * expect && cap < ((size_t)1 << 20)) cap <<= 1;
+    slots_.assign(cap, kEmpty);
+  }
+  // index of the group of (cls, plan) in groups, created (count 0) on first use
+  uint32_t find(std::vector<TaskGroup>& groups, const TaskClass& c, const uint64_t* plan) {
+    if (2 * (groups.size() + 1) > slots_.size()) grow(groups);
+    const uint64_t key = ((uint64_t)(uintptr_t)plan << 12) ^ c.cls;
+    size_t i = mix(key) & (slots_.size() - 1);
+    for (;;) {
+      const uint32_t g = slots_[i];
+      if (g == kEmpty) {
+        groups.push_back(TaskGroup{c.cost, c.cls, plan, 0, 0});
+        slots_[i] = (uint32_t)(groups.size() - 1);
+        return slots_[i];
+      }
+      if (groups[g].cls == c.cls && groups[g].plan == plan) return g;
+      i = (i + 1) & (slots_.size() - 1);
+    }
+  }
+
+ private:
+  static constexpr uint32_t kEmpty = 0xffffffffu;
+  static size_t mix(uint64_t x) {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    return (size_t)x;
+  }
+  void grow(const std::vector<TaskGroup>& groups) {
+    slots_.assign(slots_.size() * 2, kEmpty);
+    for (uint32_t g = 0; g < groups.size(); ++g) {
+      const uint64_t key = ((uint64_t)(uintptr_t)groups[g].plan << 12) ^ groups[g].cls;
+      size_t i = mix(key) & (slots_.size() - 1);
+      while (slots_[i] != kEmpty) i = (i + 1) & (slots_.size() - 1);
+      slots_[i] = g;
+    }
+  }
+  std::vector<uint32_t> slots_;
+};
+
 static ntt_status stage_units(ntt_batch* b, const std::vector<BatchTask>& list, size_t* staged) {
   const size_t n = list.size();
   std::vector<TaskClass> cl(n);
-  std::vector<size_t> order(n);
+  std::vector<uint32_t> gid(n);
+  std::vector<TaskGroup> groups;
+  GroupTable table(64);
   for (size_t k = 0; k < n; ++k) {
     cl[k] = classify(list[k]);
-    order[k] = k;
+    gid[k] = table.find(groups, cl[k], list[k].plan);
+    ++groups[gid[k]].count;
   }
-  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
-    if (cl[x].cost != cl[y].cost) return cl[x].cost > cl[y].cost;
-    if (cl[x].cls != cl[y].cls) return cl[x].cls < cl[y].cls;
-    return list[x].plan < list[y].plan;
+  // groups in block order, then each task at its group's next slot (item order within a group)
+  std::vector<uint32_t> gorder(groups.size());
+  for (uint32_t g = 0; g < groups.size(); ++g) gorder[g] = g;
+  std::sort(gorder.begin(), gorder.end(), [&](uint32_t x, uint32_t y) {
+    const TaskGroup &a = groups[x], &c = groups[y];
+    if (a.cost != c.cost) return a.cost > c.cost;
+    if (a.cls != c.cls) return a.cls < c.cls;
+    return a.plan < c.plan;
   });
+  uint32_t pos = 0;
+  for (uint32_t g : gorder) {
+    groups[g].next = pos;
+    pos += groups[g].count;
+  }
+  std::vector<size_t> order(n);
+  for (size_t k = 0; k < n; ++k) order[groups[gid[k]].next++] = k;
   BatchTask* dst = staged_tasks(b);
   BatchHead* head = staged_head(b);
   std::vector<BatchBlock> p0, p1;
@@ -559,7 +630,6 @@ static ntt_status stage_units(ntt_batch* b, const std::vector<BatchTask>& list, 
 ntt_status batch_prepare(ntt_batch* b, const ntt_batch_item* items, size_t count, size_t* out_count) {
   ntt_status st0 = wait_staging(b);
   if (st0) return st0;
-  std::vector<std::pair<uint64_t, size_t>> order(count);
   for (size_t i = 0; i < count; ++i) {
     const ntt_batch_item& it = items[i];
     if (!it.out || !it.in) return NTT_EINVAL_POINTER;
@@ -586,20 +656,25 @@ ntt_status batch_prepare(ntt_batch* b, const ntt_batch_item* items, size_t count
           return NTT_EALIAS;
       }
     }
-    order[i] = {task_cost((uint32_t)logN, it.op), i};
   }
-  std::stable_sort(order.begin(), order.end(),
-                   [](const std::pair<uint64_t, size_t>& a, const std::pair<uint64_t, size_t>& c) {
-                     return a.first > c.first;
-                   });
-  std::map<std::pair<uint64_t, uint64_t>, const ntt_plan*> seen;   // one cache lookup per distinct (N, q)
+  // in item order: the staging sorts the tasks into class blocks.  One library cache lookup per
+  // distinct (N, q), remembered in a small direct-mapped table in front of a map.
+  struct Seen { uint64_t N, q; const ntt_plan* p; };
+  Seen recent[64] = {};
+  std::map<std::pair<uint64_t, uint64_t>, const ntt_plan*> seen;
   std::vector<BatchTask> list(count);
   for (size_t k = 0; k < count; ++k) {
-    const ntt_batch_item& it = items[order[k].second];
-    const ntt_plan*& p = seen[{it.N, it.q}];
+    const ntt_batch_item& it = items[k];
+    Seen& r = recent[(it.q ^ (it.q >> 17) ^ it.N) & 63u];
+    const ntt_plan* p = (r.p && r.N == it.N && r.q == it.q) ? r.p : nullptr;
     if (!p) {
-      ntt_status st = cached_plan(it.N, it.q, &p);
-      if (st) return st;
+      const ntt_plan*& m = seen[{it.N, it.q}];
+      if (!m) {
+        ntt_status st = cached_plan(it.N, it.q, &m);
+        if (st) return st;
+      }
+      p = m;
+      r = Seen{it.N, it.q, p};
     }
     BatchTask& t = list[k];
     uint32_t op = 0, in_f = 1;
@@ -626,31 +701,47 @@ int batch_grid(const ntt_batch* b, size_t count) {
   return g < 1 ? 1 : g;
 }
 
-// Enqueues [descriptor copy of `staged` units, counter reset, phase 0, phase 1]
-// on `stream`; `phase1` false leaves out the second launch (nothing was split).
-ntt_status batch_enqueue(ntt_batch* b, size_t staged, int grid, hipStream_t stream, bool phase1) {
+// Copies the staged head and `staged` descriptors to the device, on the
+// context's copy stream (ordered before `stream`'s next work by an event, so it
+// overlaps whatever `stream` is still running; the staging set it overwrites
+// is idle, see wait_staging), or on `stream` itself.
+static ntt_status batch_copy(ntt_batch* b, size_t staged, hipStream_t stream) {
   ntt_batch_stage& g = cur_stage(b);
-  if (hipMemcpyAsync(g.dev + kDevHead, g.host, stage_bytes(staged), hipMemcpyHostToDevice, stream) != hipSuccess)
-    return NTT_EDEVICE;
+  if (b->copy_stream) {
+    if (hipMemcpyAsync(g.dev + kDevHead, g.host, stage_bytes(staged), hipMemcpyHostToDevice, b->copy_stream) !=
+            hipSuccess ||
+        hipEventRecord(g.copied, b->copy_stream) != hipSuccess || hipStreamWaitEvent(stream, g.copied, 0) != hipSuccess)
+      return NTT_EDEVICE;
+    return NTT_OK;
+  }
+  return hipMemcpyAsync(g.dev + kDevHead, g.host, stage_bytes(staged), hipMemcpyHostToDevice, stream) == hipSuccess
+             ? NTT_OK
+             : NTT_EDEVICE;
+}
+
+// Enqueues [phase 0, phase 1] on `stream`; `phase1` false leaves out the second
+// launch (nothing was split).
+ntt_status batch_enqueue(ntt_batch* b, int grid, hipStream_t stream, bool phase1) {
+  ntt_batch_stage& g = cur_stage(b);
   u32* counter = reinterpret_cast<u32*>(g.dev);
   const BatchHead* head = reinterpret_cast<const BatchHead*>(g.dev + kDevHead);
   const BatchTask* tasks = reinterpret_cast<const BatchTask*>(g.dev + kDevHead + kStageHead);
-  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, stream, counter);
   hipLaunchKernelGGL(ntt_batch_kernel, dim3(grid), dim3(kBatchThreads), 0, stream, tasks, head, counter, 0u);
   if (phase1) hipLaunchKernelGGL(ntt_batch_kernel, dim3(grid), dim3(kBatchThreads), 0, stream, tasks, head, counter, 1u);
   return hipGetLastError() == hipSuccess ? NTT_OK : NTT_EDEVICE;
 }
 
 static ntt_status batch_launch_staged(ntt_batch* b, size_t n, hipStream_t s, bool graph) {
-  ntt_status st = NTT_OK;
   ntt_batch_stage& sg = cur_stage(b);
+  ntt_status st = batch_copy(b, n, s);
+  if (st) return st;
   if (!graph) {
     const BatchHead* head = reinterpret_cast<const BatchHead*>(sg.host);
-    st = batch_enqueue(b, n, batch_grid(b, std::max(head->units[0], head->units[1])), s, head->units[1] != 0);
+    st = batch_enqueue(b, batch_grid(b, std::max(head->units[0], head->units[1])), s, head->units[1] != 0);
     if (st) return st;
   } else {
     if (!sg.graph_exec) {
-      // captured once per staging set with the full-capacity copy and grid; the kernel reads the count from device memory
+      // captured once per staging set with the full grid; the kernels read the blocks and counts from device memory
       const int grid = batch_grid(b, (size_t)1 << 30);
       hipStream_t cap = nullptr;
       if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return NTT_EDEVICE;
@@ -658,7 +749,7 @@ static ntt_status batch_launch_staged(ntt_batch* b, size_t n, hipStream_t s, boo
         (void)hipStreamDestroy(cap);
         return NTT_EDEVICE;
       }
-      st = batch_enqueue(b, b->capacity, grid, cap, true);
+      st = batch_enqueue(b, grid, cap, true);
       hipGraph_t g = nullptr;
       const hipError_t e = hipStreamEndCapture(cap, &g);
       (void)hipStreamDestroy(cap);
@@ -672,22 +763,7 @@ static ntt_status batch_launch_staged(ntt_batch* b, size_t n, hipStream_t s, boo
         return NTT_EDEVICE;
       }
       sg.graph = g;
-      // find the descriptor copy, so each replay copies only its own batch's descriptors
-      size_t nn = 0;
-      sg.copy_node = nullptr;
-      if (hipGraphGetNodes(g, nullptr, &nn) == hipSuccess && nn > 0) {
-        std::vector<hipGraphNode_t> nodes(nn);
-        if (hipGraphGetNodes(g, nodes.data(), &nn) == hipSuccess) {
-          for (size_t i = 0; i < nn; ++i) {
-            hipGraphNodeType ty;
-            if (hipGraphNodeGetType(nodes[i], &ty) == hipSuccess && ty == hipGraphNodeTypeMemcpy) sg.copy_node = nodes[i];
-          }
-        }
-      }
     }
-    if (sg.copy_node && hipGraphExecMemcpyNodeSetParams1D(sg.graph_exec, sg.copy_node, sg.dev + kDevHead, sg.host,
-                                                          stage_bytes(n), hipMemcpyHostToDevice) != hipSuccess)
-      sg.copy_node = nullptr;                      // keep the captured full-capacity copy from here on
     if (hipGraphLaunch(sg.graph_exec, s) != hipSuccess) return NTT_EDEVICE;
   }
   if (hipEventRecord(sg.done, s) != hipSuccess) return NTT_EDEVICE;
@@ -701,14 +777,7 @@ ntt_status batch_launch_tasks(ntt_batch* b, const BatchTask* tasks, size_t count
   if (count > b->capacity) return NTT_EINVAL_COUNT;
   ntt_status st = wait_staging(b);
   if (st) return st;
-  std::vector<std::pair<uint64_t, size_t>> order(count);
-  for (size_t i = 0; i < count; ++i) order[i] = {task_cost(tasks[i].logN, tasks[i].op), i};
-  std::stable_sort(order.begin(), order.end(),
-                   [](const std::pair<uint64_t, size_t>& a, const std::pair<uint64_t, size_t>& c) {
-                     return a.first > c.first;
-                   });
-  std::vector<BatchTask> list(count);
-  for (size_t k = 0; k < count; ++k) list[k] = tasks[order[k].second];
+  std::vector<BatchTask> list(tasks, tasks + count);
   size_t n = 0;
   st = stage_units(b, list, &n);
   if (st) return st;
@@ -770,6 +839,7 @@ static void release_stage(ntt_batch_stage& g) {
   if (g.graph_exec) (void)hipGraphExecDestroy(g.graph_exec);
   if (g.graph) (void)hipGraphDestroy(g.graph);
   if (g.done) (void)hipEventDestroy(g.done);
+  if (g.copied) (void)hipEventDestroy(g.copied);
   if (g.dev) (void)hipFree(g.dev);
   if (g.host) (void)hipHostFree(g.host);
   g = ntt_batch_stage{};
@@ -789,12 +859,17 @@ ntt_status ntt_batch_create(ntt_batch** out, size_t capacity) {
     if (hipHostMalloc((void**)&g.host, bytes, hipHostMallocDefault) != hipSuccess) { g.host = nullptr; st = NTT_ENOMEM; }
     if (!st && hipMalloc((void**)&g.dev, dev_bytes(b)) != hipSuccess) { g.dev = nullptr; st = NTT_ENOMEM; }
     if (!st && hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess) { g.done = nullptr; st = NTT_EDEVICE; }
+    if (!st && hipEventCreateWithFlags(&g.copied, hipEventDisableTiming) != hipSuccess) { g.copied = nullptr; st = NTT_EDEVICE; }
+    // the claim counters start at zero; every phase leaves them at zero
+    if (!st && hipMemset(g.dev, 0, kDevHead) != hipSuccess) st = NTT_EDEVICE;
     if (st) {
       for (ntt_batch_stage& h : b->stage) release_stage(h);
+      if (b->copy_stream) (void)hipStreamDestroy(b->copy_stream);
       delete b;
       return st;
     }
   }
+  if (hipStreamCreateWithFlags(&b->copy_stream, hipStreamNonBlocking) != hipSuccess) b->copy_stream = nullptr;
   *out = b;
   return NTT_OK;
 }
@@ -802,6 +877,7 @@ ntt_status ntt_batch_create(ntt_batch** out, size_t capacity) {
 ntt_status ntt_batch_destroy(ntt_batch* b) {
   if (!b) return NTT_EINVAL_POINTER;
   for (ntt_batch_stage& g : b->stage) release_stage(g);
+  if (b->copy_stream) (void)hipStreamDestroy(b->copy_stream);
   delete b;
   return NTT_OK;
 }
