@@ -80,12 +80,15 @@ typedef void (*PassKernel)(const PassArgs);
 // N = N1 N2 (Section 2.2) one index bit either way: the low pass covers one
 // bit fewer or one more than the default (reading the natural table), the
 // high pass the rest, with 8 columns per tile where its tile would otherwise
-// exceed 1024 threads of 8 coefficients.
-constexpr int kVariants = 8;
-struct VariantShape { int hi, lo; bool hand; int dlo; };
+// exceed 1024 threads of 8 coefficients.  Variants 8 and 9 halve both passes'
+// tiles (half the columns per high-pass tile, half the blocks per low-pass
+// tile): twice the workgroups, for batches too small to fill the chip.
+constexpr int kVariants = 10;
+struct VariantShape { int hi, lo; bool hand; int dlo; int half; };
 static constexpr VariantShape kVariantShape[kVariants] = {
-    {4, 4, true, 0}, {3, 4, true, 0}, {2, 4, true, 0}, {3, 3, true, 0},
-    {2, 3, true, 0}, {2, 2, false, 0}, {3, 4, true, -1}, {3, 4, true, 1}};
+    {4, 4, true, 0, 0}, {3, 4, true, 0, 0}, {2, 4, true, 0, 0}, {3, 3, true, 0, 0},
+    {2, 3, true, 0, 0}, {2, 2, false, 0, 0}, {3, 4, true, -1, 0}, {3, 4, true, 1, 0},
+    {3, 4, true, 0, 1}, {2, 4, true, 0, 1}};
 // Index bits of the low pass for a variant, and columns per high-pass tile.
 static int variant_lt_lo(int logN, int variant) { return mp_logt_lo(logN) + kVariantShape[variant].dlo; }
 __host__ __device__ constexpr int hi_logc(int lt_hi) { return lt_hi >= 10 ? 3 : 4; }
@@ -97,11 +100,13 @@ static int hi_logr(int logN, int variant) {
   return hi_logr_clamped(logN - variant_lt_lo(logN, variant), kVariantShape[variant].hi);
 }
 static int lo_logr(int variant) { return kVariantShape[variant].lo; }
+static int variant_half(int variant) { return kVariantShape[variant].half; }
 
-template <bool FWD, int LOGN, int MODE, bool LAST, int LOGR0, bool HAND = true, int LTLO = mp_logt_lo(LOGN)>
+template <bool FWD, int LOGN, int MODE, bool LAST, int LOGR0, bool HAND = true, int LTLO = mp_logt_lo(LOGN),
+          int HALF = 0>
 static PassKernel pick_hi_r() {
   constexpr int LT = LOGN - LTLO;
-  constexpr int LC = hi_logc(LT);
+  constexpr int LC = hi_logc(LT) - HALF;
   constexpr int LOGR = hi_logr_clamped(LT, LOGR0);
   // register budget: 64 VGPRs for the 64-VGPR schedule, else 128 (256 for the widest tiles)
   constexpr int MW = !HAND ? 8 : (LOGR >= 4 && LT >= 9 ? 2 : 4);
@@ -112,6 +117,10 @@ static PassKernel pick_hi(int variant) {
   if (kVariantShape[variant].dlo < 0) return pick_hi_r<FWD, LOGN, MODE, LAST, 3, true, mp_logt_lo(LOGN) - 1>();
   if (kVariantShape[variant].dlo > 0) return pick_hi_r<FWD, LOGN, MODE, LAST, 3, true, mp_logt_lo(LOGN) + 1>();
   if (!kVariantShape[variant].hand) return pick_hi_r<FWD, LOGN, MODE, LAST, 2, false>();
+  if (kVariantShape[variant].half) {
+    if (kVariantShape[variant].hi == 3) return pick_hi_r<FWD, LOGN, MODE, LAST, 3, true, mp_logt_lo(LOGN), 1>();
+    return pick_hi_r<FWD, LOGN, MODE, LAST, 2, true, mp_logt_lo(LOGN), 1>();
+  }
   switch (kVariantShape[variant].hi) {
     case 4: return pick_hi_r<FWD, LOGN, MODE, LAST, 4>();
     case 3: return pick_hi_r<FWD, LOGN, MODE, LAST, 3>();
@@ -124,6 +133,8 @@ static PassKernel pick_lo(int variant) {
   constexpr int LH = 12 - LT;                          // 4096-coefficient tiles
   if (kVariantShape[variant].dlo < 0) return ntt_tile_kernel<FWD, LT - 1, kMpLogrLo, 0, LH + 1, 4, MODE, LAST, -1>;
   if (kVariantShape[variant].dlo > 0) return ntt_tile_kernel<FWD, LT + 1, kMpLogrLo, 0, LH - 1, 4, MODE, LAST, -1>;
+  if (kVariantShape[variant].half)
+    return ntt_tile_kernel<FWD, LT, kMpLogrLo, 0, LH - 1, 4, MODE, LAST, mp_perm_top(FWD, LOGN)>;
   if (lo_logr(variant) == kMpLogrLo) return ntt_tile_kernel<FWD, LT, kMpLogrLo, 0, LH, 4, MODE, LAST, mp_perm_top(FWD, LOGN)>;
   if (!kVariantShape[variant].hand) return ntt_tile_kernel<FWD, LT, 2, 0, LH, 8, MODE, LAST, -1, false>;
   return ntt_tile_kernel<FWD, LT, 3, 0, LH, 4, MODE, LAST, -1>;
@@ -232,13 +243,13 @@ static ntt_status launch_passes(const NttLaunch& l, bool fwd, int force_variant)
     uint64_t tiles;
     if (hi) {
       a.b0 = (u32)lt_lo;
-      const int logr = hi_logr(logN, variant), logc = hi_logc(lt_hi);
+      const int logr = hi_logr(logN, variant), logc = hi_logc(lt_hi) - variant_half(variant);
       nt = 1 << (lt_hi + logc - logr);
       tiles = (1ull << lt_lo) >> logc;
     } else {
       a.b0 = 0;
-      nt = 1 << (12 - lo_logr(variant));
-      tiles = 1ull << (logN - 12);
+      nt = 1 << (12 - variant_half(variant) - lo_logr(variant));
+      tiles = 1ull << (logN - 12 + variant_half(variant));
     }
     for (uint64_t it0 = 0; it0 < items; it0 += kMaxY) {
       const uint64_t ny = (items - it0) < kMaxY ? (items - it0) : kMaxY;
