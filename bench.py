@@ -46,7 +46,7 @@ HBM_PEAK_GBS = 8000.0
 # Valid only for the kernel sources they were taken with, identified by the SHA-256 of these files.
 COUNTERS_N16384 = {
     "sources": ["ntt_onchip.hip", "ntt_onchip.h", "ntt_common.h", "modarith.h", "internal.h", "ntt_kernels.hip"],
-    "sha256": "4fbee85ab26b41aac93445d4a940af8a21da911bdce8657a134b52dbbba67de3",
+    "sha256": "8e25249760b9ae828702284c74b877e05de0cd9d0c6094f887ea2e4d4e25482e",
     "fetch_scale": 2.0, "write_scale": 1.0,
     "product": {"fetch_kib": 886963.8, "write_kib": 540672.0, "valu_insts": 394428416},
     "forward": {"fetch_kib": 294642.5, "write_kib": 581632.0, "valu_insts": 145195008},
