@@ -156,6 +156,8 @@ ntt_status launch_eltwise_fma(const EltLaunch& l);                // b = addend 
 // Persistent batch launch of already-resolved tasks (ntt_batch.hip); sorts them
 // into class blocks in the context's staging buffer.
 ntt_status batch_launch_tasks(ntt_batch* b, const BatchTask* tasks, size_t count, hipStream_t stream, bool graph);
+// Copies of the descriptors on the context's own stream (the default) or on the launch stream.
+void batch_use_copy_stream(ntt_batch* b, bool on);
 ntt_status launch_eltwise_add(const EltLaunch& l);
 
 // Word-size-2^32 transforms for moduli below 2^30 (ntt_small.hip): single pass

@@ -52,7 +52,8 @@ struct ntt_batch {
   size_t capacity;                 // tasks
   int grid;                        // persistent workgroups (0: automatic)
   int cur;                         // staging set of the next run
-  hipStream_t copy_stream;         // plain runs copy their descriptors here, overlapping the previous run
+  hipStream_t copy_stream;         // runs copy their descriptors here, overlapping the previous run
+  bool use_copy_stream;            // off: copies go on the launch stream (callers that own several streams)
   ntt_batch_stage stage[2];
 };
 
@@ -705,9 +706,16 @@ int batch_grid(const ntt_batch* b, size_t count) {
 // context's copy stream (ordered before `stream`'s next work by an event, so it
 // overlaps whatever `stream` is still running; the staging set it overwrites
 // is idle, see wait_staging), or on `stream` itself.
+void batch_use_copy_stream(ntt_batch* b, bool on) { b->use_copy_stream = on; }
+
 static ntt_status batch_copy(ntt_batch* b, size_t staged, hipStream_t stream) {
   ntt_batch_stage& g = cur_stage(b);
-  if (b->copy_stream) {
+  if (b->use_copy_stream && !b->copy_stream &&
+      hipStreamCreateWithFlags(&b->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+    b->copy_stream = nullptr;
+    b->use_copy_stream = false;                     // copies go on the launch stream
+  }
+  if (b->use_copy_stream) {
     if (hipMemcpyAsync(g.dev + kDevHead, g.host, stage_bytes(staged), hipMemcpyHostToDevice, b->copy_stream) !=
             hipSuccess ||
         hipEventRecord(g.copied, b->copy_stream) != hipSuccess || hipStreamWaitEvent(stream, g.copied, 0) != hipSuccess)
@@ -869,7 +877,7 @@ ntt_status ntt_batch_create(ntt_batch** out, size_t capacity) {
       return st;
     }
   }
-  if (hipStreamCreateWithFlags(&b->copy_stream, hipStreamNonBlocking) != hipSuccess) b->copy_stream = nullptr;
+  b->use_copy_stream = true;                        // the stream itself is created on first use
   *out = b;
   return NTT_OK;
 }

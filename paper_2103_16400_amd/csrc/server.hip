@@ -627,6 +627,8 @@ ntt_status ntt_server_create(ntt_server** out, const ntt_server_config* config) 
         hipEventCreateWithFlags(&sl.event, hipEventDisableTiming) != hipSuccess)
       e = NTT_EDEVICE;
     if (!e && c.mode == NTT_SERVE_BATCHED) e = ntt_batch_create(&sl.batch, c.max_batch_tasks);
+    // the server's slots already spread over the hardware queues: no extra copy stream per slot
+    if (!e && sl.batch) batch_use_copy_stream(sl.batch, false);
     if (e) {
       destroy_resources(s.get());
       return e;

@@ -843,6 +843,30 @@ def test_batch_graph_replays(nt):
     batch.close()
 
 
+def test_batch_counters_across_grids_and_modes(nt):
+    """Each phase's claim counter is cleared by the workgroup that draws the phase's last claim
+    (units + grid - 1), so it must hold whatever the grid and however plain and graph-replayed
+    runs alternate: a grid smaller than the units, one larger than them, a change of grid between
+    runs, batches with and without a second phase, all against the oracle."""
+    moduli = PRIMES["uneven"]["moduli"]
+    with_split = [(nt.BATCH_FWD_LAZY, 12 + (k % 4), moduli[k % 16]) for k in range(9)]   # 2^15 limbs too
+    no_split = [(nt.BATCH_INV, 10 + (k % 3), moduli[(5 * k) % 16]) for k in range(7)]
+    cases = [_batch_case(nt, 150, with_split), _batch_case(nt, 151, no_split)]
+    batch = nt.Batch(16)
+    import torch
+    for rnd, (grid, graph) in enumerate([(0, False), (3, False), (3, True), (1000, False), (1000, True),
+                                         (0, True), (5, False)]):
+        batch.set_grid(grid)
+        for tasks, host in cases:
+            for t in tasks:
+                t[1].zero_()
+            torch.cuda.synchronize()
+            batch.run(tasks, graph=graph)
+            torch.cuda.synchronize()
+            _check_batch_outputs(nt, tasks, host)
+    batch.close()
+
+
 def test_batch_one_shot_calls(nt):
     """ntt_batch_forward / _inverse / _product: uneven task lists of one kind through the
     library-owned per-thread context (grown past its first size), against the oracle;
