@@ -204,6 +204,7 @@ def time_uneven_batch(nt, torch, primes, reps=10):
     for name, op in (("fwd", nt.BATCH_FWD_LAZY), ("inv", nt.BATCH_INV)):
         items, cnt = nt.Batch.make_items([(op, d, s_, None, None, N, q) for s_, d, N, q in views])
         res[name + "_grid"] = batch.autotune(items, cnt, stream=stream)
+        res[name + "_shape"] = batch.config()[1]
         for mode in ("batched", "graph"):
             batch.run(items, cnt, stream=stream, graph=(mode == "graph"))
             torch.cuda.synchronize()

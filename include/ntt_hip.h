@@ -389,6 +389,15 @@ ntt_status poly_mul_acc_ntt_rns32(uint32_t* acc, const uint32_t* a_ntt, const ui
  *   copies its own descriptors on a stream of the context, ordered before the
  *   kernels by an event.
  * ntt_batch_set_grid: number of persistent workgroups (0 = two per CU).
+ * ntt_batch_set_shape: per-limb shape of the transform units staged from then
+ *   on: 0 (default) the per-call kernels' own (16 or 32 coefficients per
+ *   thread, several limbs per workgroup below 2^14, tiles of 16 per thread);
+ *   1 twice the threads per limb or tile (for N <= 2^13 and for the tiles of
+ *   N >= 2^15; N = 2^14 transforms and products keep shape 0).  Results are
+ *   the same words either way.  NTT_EINVAL_COUNT for another value.
+ * ntt_batch_get_config: the context's workgroup count (0 = automatic) and
+ *   unit shape, as set or chosen by ntt_batch_autotune (either pointer may be
+ *   NULL).
  */
 typedef struct ntt_batch ntt_batch;
 #define NTT_BATCH_FWD_LAZY 0u
@@ -410,10 +419,13 @@ typedef struct {
 ntt_status ntt_batch_create(ntt_batch** batch, size_t capacity);
 ntt_status ntt_batch_destroy(ntt_batch* batch);
 ntt_status ntt_batch_set_grid(ntt_batch* batch, int workgroups);
+ntt_status ntt_batch_set_shape(ntt_batch* batch, int shape);
+ntt_status ntt_batch_get_config(const ntt_batch* batch, int* workgroups, int* shape);
 ntt_status ntt_batch_run(ntt_batch* batch, const ntt_batch_item* items, size_t count, ntt_stream_t stream);
 ntt_status ntt_batch_run_graph(ntt_batch* batch, const ntt_batch_item* items, size_t count, ntt_stream_t stream);
 /* Times the persistent launch of this batch with one, one and a half and two
- * workgroups per CU and keeps the fastest grid for the context (the chosen
+ * workgroups per CU, each with both unit shapes (ntt_batch_set_shape), and
+ * keeps the fastest grid and shape for the context (the chosen workgroup
  * count in *chosen, may be NULL).  Runs the batch several times, so every
  * task must have out != in (NTT_EALIAS otherwise); outputs end up holding the
  * batch's result.  Synchronises `stream`. */

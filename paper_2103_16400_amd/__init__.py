@@ -53,6 +53,8 @@ _SIGS = {
     "ntt_batch_create": (_ST, [ctypes.POINTER(_P), ctypes.c_size_t]),
     "ntt_batch_destroy": (_ST, [_P]),
     "ntt_batch_set_grid": (_ST, [_P, ctypes.c_int]),
+    "ntt_batch_set_shape": (_ST, [_P, ctypes.c_int]),
+    "ntt_batch_get_config": (_ST, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "ntt_batch_run": (_ST, [_P, _P, ctypes.c_size_t, _P]),
     "ntt_batch_run_graph": (_ST, [_P, _P, ctypes.c_size_t, _P]),
     "ntt_batch_autotune": (_ST, [_P, _P, ctypes.c_size_t, _P, ctypes.POINTER(ctypes.c_int)]),
@@ -330,6 +332,16 @@ class Batch:
 
     def set_grid(self, workgroups: int):
         _check(_lib.ntt_batch_set_grid(self._h, workgroups), "ntt_batch_set_grid")
+
+    def set_shape(self, shape: int):
+        """0: the per-call kernels' shapes; 1: twice the threads per limb or tile."""
+        _check(_lib.ntt_batch_set_shape(self._h, shape), "ntt_batch_set_shape")
+
+    def config(self):
+        """(workgroups, shape) of the context (workgroups 0 = automatic)."""
+        g, sh = ctypes.c_int(0), ctypes.c_int(0)
+        _check(_lib.ntt_batch_get_config(self._h, ctypes.byref(g), ctypes.byref(sh)), "ntt_batch_get_config")
+        return g.value, sh.value
 
     @staticmethod
     def make_items(tasks):

@@ -51,6 +51,7 @@ struct ntt_batch {
   int device;
   size_t capacity;                 // tasks
   int grid;                        // persistent workgroups (0: automatic)
+  int shape;                       // per-limb shape of transform units: 0 the single-pass kernel's, 1 twice the threads
   int cur;                         // staging set of the next run
   hipStream_t copy_stream;         // runs copy their descriptors here, overlapping the previous run
   bool use_copy_stream;            // off: copies go on the launch stream (callers that own several streams)
@@ -59,7 +60,7 @@ struct ntt_batch {
 
 namespace nttamd {
 
-// Block classes: BatchBlock::cls = kind | logN << 3 | op << 8 | wide << 11.
+// Block classes: BatchBlock::cls = kind | logN << 3 | op << 8 | wide << 11 | shape << 12.
 enum : uint32_t { kClassOnchip = 0, kClassProduct = 1, kClassTile0 = 2, kClassTile1 = 3 };
 // A run of units of one class within a phase.
 struct BatchBlock {
@@ -104,7 +105,11 @@ constexpr int kBatchLdsWords32 = 17408;
 // single-pass kernel's own shape, 2^onchip_logr(logN) coefficients per thread;
 // or two 4096-coefficient tiles of one pass of a split two-pass transform.
 
-__host__ __device__ constexpr int onchip_groups(int logN) { return kBatchThreads / ((1 << logN) >> onchip_logr(logN)); }
+// Shape 1 gives a limb (or tile) twice the threads of shape 0, with half the coefficients each.
+__host__ __device__ constexpr int batch_logr(int logN, int shape) { return onchip_logr(logN) - shape; }
+__host__ __device__ constexpr int onchip_groups(int logN, int shape = 0) {
+  return kBatchThreads / ((1 << logN) >> batch_logr(logN, shape));
+}
 
 // Every sub-group is a whole number of waves, so the sub-task index, the
 // descriptor and its plan are wave-uniform: taken through readfirstlane they
@@ -197,13 +202,14 @@ __device__ __forceinline__ u32 run_block(const BatchBlock& bk_in, u32* ctr_in, u
 }
 
 // Whole single-pass transforms (N <= 2^14).
-template <bool FWD, int LOGN, int MODE, bool WIDE>
+template <bool FWD, int LOGN, int MODE, bool WIDE, int SHAPE = 0>
 __device__ __attribute__((noinline)) u32 class_onchip(const BatchTask* tasks, const BatchBlock bk, u32* ctr,
                                                       u32* claimed, u32 u, u32* lds) {
-  constexpr int LOGR = onchip_logr(LOGN);
+  constexpr int LOGR = batch_logr(LOGN, SHAPE);
   constexpr bool SPLIT = LOGN >= 13;
   using K = OnChip<FWD, LOGN, LOGR, SPLIT, true, WIDE>;
-  constexpr int G = onchip_groups(LOGN);
+  constexpr int G = onchip_groups(LOGN, SHAPE);
+  static_assert(G >= 1, "a limb needs more threads than a workgroup has");
   static_assert(G * K::LDSW * sizeof(typename K::W) <= kBatchLdsWords32 * 4, "sub-group exchange buffers exceed LDS");
   return run_block(bk, ctr, claimed, u, G, [&](u32 k, u32 t, bool active, u32 h) {
     const BatchTask tk = load_task(tasks, rfl(bk.desc0 + k));
@@ -286,7 +292,7 @@ __device__ __attribute__((noinline)) u32 class_product_twopass(const BatchTask* 
 // threads and 16 coefficients each, the multi-pass kernels' own tile shape (the
 // low pass reads the transposed sub-tables).  Sub-task k is tile k mod T of the
 // block's task k / T, T = N / 4096.
-template <bool FWD, int LOGN, int MODE, int PASS>
+template <bool FWD, int LOGN, int MODE, int PASS, int SHAPE = 0>
 __device__ __attribute__((noinline)) u32 class_tile(const BatchTask* tasks, const BatchBlock bk, u32* ctr,
                                                     u32* claimed, u32 u, u32* lds) {
   constexpr int LT_LO = mp_logt_lo(LOGN);
@@ -295,24 +301,28 @@ __device__ __attribute__((noinline)) u32 class_tile(const BatchTask* tasks, cons
   constexpr int LH_LO = 12 - LT_LO;
   constexpr int TSH = LOGN - 12;
   constexpr bool HI = FWD ? PASS == 0 : PASS == 1;
-  constexpr int PTOP = mp_perm_top(FWD, LOGN);
-  constexpr int TILE_LDS = (4096 + 256);      // u64 words of one tile's exchange buffer at 16 per thread
-  static_assert(2 * TILE_LDS * 2 <= kBatchLdsWords32, "tile exchange buffers exceed LDS");
-  return run_block(bk, ctr, claimed, u, 2, [&](u32 k, u32 t, bool active, u32 h) {
+  // shape 0: 16 coefficients per thread, the low pass on the transposed sub-tables; shape 1: 8,
+  // twice the threads per tile, natural tables
+  constexpr int LOGR = kMpLogrLo - SHAPE;
+  constexpr int PTOP = SHAPE == 0 ? mp_perm_top(FWD, LOGN) : -1;
+  constexpr int G = kBatchThreads / (4096 >> LOGR);
+  constexpr int TILE_LDS = 4096 + (4096 >> LOGR);   // u64 words of one tile's exchange buffer
+  static_assert(G * TILE_LDS * 2 <= kBatchLdsWords32, "tile exchange buffers exceed LDS");
+  return run_block(bk, ctr, claimed, u, G, [&](u32 k, u32 t, bool active, u32 h) {
     const BatchTask tk = load_task(tasks, rfl(bk.desc0 + (k >> TSH)));
     const u32 tile = rfl(k & ((1u << TSH) - 1u));
     const PlanView pv = load_plan_batch(tk.plan, FWD, 1ull << LOGN);
     u64* l = reinterpret_cast<u64*>(lds) + h * TILE_LDS;
     if constexpr (HI) {
       if constexpr (PASS == 0)
-        tile_body<FWD, LT_HI, kMpLogrLo, LC_HI, 0, kOutLazy, false, -1, true>(pv, LOGN, LT_LO, tile, tk.in, tk.out, nullptr, l, true, t, active);
+        tile_body<FWD, LT_HI, LOGR, LC_HI, 0, kOutLazy, false, -1, true>(pv, LOGN, LT_LO, tile, tk.in, tk.out, nullptr, l, true, t, active);
       else
-        tile_body<FWD, LT_HI, kMpLogrLo, LC_HI, 0, MODE, true, -1, true>(pv, LOGN, LT_LO, tile, tk.out, tk.out, nullptr, l, false, t, active);
+        tile_body<FWD, LT_HI, LOGR, LC_HI, 0, MODE, true, -1, true>(pv, LOGN, LT_LO, tile, tk.out, tk.out, nullptr, l, false, t, active);
     } else {
       if constexpr (PASS == 0)
-        tile_body<FWD, LT_LO, kMpLogrLo, 0, LH_LO, kOutLazy, false, PTOP, true>(pv, LOGN, 0, tile, tk.in, tk.out, nullptr, l, true, t, active);
+        tile_body<FWD, LT_LO, LOGR, 0, LH_LO, kOutLazy, false, PTOP, true>(pv, LOGN, 0, tile, tk.in, tk.out, nullptr, l, true, t, active);
       else
-        tile_body<FWD, LT_LO, kMpLogrLo, 0, LH_LO, MODE, true, PTOP, true>(pv, LOGN, 0, tile, tk.out, tk.out, nullptr, l, false, t, active);
+        tile_body<FWD, LT_LO, LOGR, 0, LH_LO, MODE, true, PTOP, true>(pv, LOGN, 0, tile, tk.out, tk.out, nullptr, l, false, t, active);
     }
   });
 }
@@ -323,8 +333,17 @@ __device__ __attribute__((noinline)) u32 class_skip(const BatchBlock bk, u32* ct
 }
 
 template <bool FWD, int MODE, bool WIDE>
-__device__ __forceinline__ u32 pick_onchip(u32 logN, const BatchTask* tasks, const BatchBlock& bk, u32* ctr,
+__device__ __forceinline__ u32 pick_onchip(u32 logN, u32 shape, const BatchTask* tasks, const BatchBlock& bk, u32* ctr,
                                            u32* claimed, u32 u, u32* lds) {
+  if (shape) {
+    switch (logN) {                            // shape 1 exists where a limb fits 512 threads
+      case 10: return class_onchip<FWD, 10, MODE, WIDE, 1>(tasks, bk, ctr, claimed, u, lds);
+      case 11: return class_onchip<FWD, 11, MODE, WIDE, 1>(tasks, bk, ctr, claimed, u, lds);
+      case 12: return class_onchip<FWD, 12, MODE, WIDE, 1>(tasks, bk, ctr, claimed, u, lds);
+      case 13: return class_onchip<FWD, 13, MODE, WIDE, 1>(tasks, bk, ctr, claimed, u, lds);
+      default: return class_skip(bk, ctr, claimed, u);
+    }
+  }
   switch (logN) {
     case 10: return class_onchip<FWD, 10, MODE, WIDE>(tasks, bk, ctr, claimed, u, lds);
     case 11: return class_onchip<FWD, 11, MODE, WIDE>(tasks, bk, ctr, claimed, u, lds);
@@ -336,24 +355,27 @@ __device__ __forceinline__ u32 pick_onchip(u32 logN, const BatchTask* tasks, con
 }
 
 template <bool FWD, int MODE, int PASS>
-__device__ __forceinline__ u32 pick_tile(u32 logN, const BatchTask* tasks, const BatchBlock& bk, u32* ctr,
+__device__ __forceinline__ u32 pick_tile(u32 logN, u32 shape, const BatchTask* tasks, const BatchBlock& bk, u32* ctr,
                                          u32* claimed, u32 u, u32* lds) {
-  switch (logN) {
-    case 15: return class_tile<FWD, 15, MODE, PASS>(tasks, bk, ctr, claimed, u, lds);
-    case 16: return class_tile<FWD, 16, MODE, PASS>(tasks, bk, ctr, claimed, u, lds);
-    case 17: return class_tile<FWD, 17, MODE, PASS>(tasks, bk, ctr, claimed, u, lds);
+  switch (logN * 2 + (shape ? 1 : 0)) {
+    case 30: return class_tile<FWD, 15, MODE, PASS>(tasks, bk, ctr, claimed, u, lds);
+    case 31: return class_tile<FWD, 15, MODE, PASS, 1>(tasks, bk, ctr, claimed, u, lds);
+    case 32: return class_tile<FWD, 16, MODE, PASS>(tasks, bk, ctr, claimed, u, lds);
+    case 33: return class_tile<FWD, 16, MODE, PASS, 1>(tasks, bk, ctr, claimed, u, lds);
+    case 34: return class_tile<FWD, 17, MODE, PASS>(tasks, bk, ctr, claimed, u, lds);
+    case 35: return class_tile<FWD, 17, MODE, PASS, 1>(tasks, bk, ctr, claimed, u, lds);
     default: return class_skip(bk, ctr, claimed, u);
   }
 }
 
 template <int PASS>
-__device__ __forceinline__ u32 pick_tile_op(u32 op, u32 logN, const BatchTask* tasks, const BatchBlock& bk, u32* ctr,
-                                            u32* claimed, u32 u, u32* lds) {
+__device__ __forceinline__ u32 pick_tile_op(u32 op, u32 logN, u32 shape, const BatchTask* tasks, const BatchBlock& bk,
+                                            u32* ctr, u32* claimed, u32 u, u32* lds) {
   switch (op) {
-    case kBatchFwdLazy: return pick_tile<true, kOutLazy, PASS>(logN, tasks, bk, ctr, claimed, u, lds);
-    case kBatchFwdCanon: return pick_tile<true, kOutCanon, PASS>(logN, tasks, bk, ctr, claimed, u, lds);
-    case kBatchInvLazy: return pick_tile<false, kOutLazy, PASS>(logN, tasks, bk, ctr, claimed, u, lds);
-    case kBatchInvCanon: return pick_tile<false, kOutCanon, PASS>(logN, tasks, bk, ctr, claimed, u, lds);
+    case kBatchFwdLazy: return pick_tile<true, kOutLazy, PASS>(logN, shape, tasks, bk, ctr, claimed, u, lds);
+    case kBatchFwdCanon: return pick_tile<true, kOutCanon, PASS>(logN, shape, tasks, bk, ctr, claimed, u, lds);
+    case kBatchInvLazy: return pick_tile<false, kOutLazy, PASS>(logN, shape, tasks, bk, ctr, claimed, u, lds);
+    case kBatchInvCanon: return pick_tile<false, kOutCanon, PASS>(logN, shape, tasks, bk, ctr, claimed, u, lds);
     default: return class_skip(bk, ctr, claimed, u);
   }
 }
@@ -362,21 +384,22 @@ __device__ __forceinline__ u32 run_class(const BatchTask* tasks, const BatchBloc
                                          u32* lds) {
   const u32 kind = bk.cls & 7u, logN = (bk.cls >> 3) & 31u, op = (bk.cls >> 8) & 7u;
   const bool wide = (bk.cls >> 11) & 1u;
+  const u32 shape = (bk.cls >> 12) & 1u;
   switch (kind) {
     case kClassOnchip:
       switch (op) {
         case kBatchFwdLazy:
-          return wide ? pick_onchip<true, kOutLazy, true>(logN, tasks, bk, ctr, claimed, u, lds)
-                      : pick_onchip<true, kOutLazy, false>(logN, tasks, bk, ctr, claimed, u, lds);
+          return wide ? pick_onchip<true, kOutLazy, true>(logN, shape, tasks, bk, ctr, claimed, u, lds)
+                      : pick_onchip<true, kOutLazy, false>(logN, shape, tasks, bk, ctr, claimed, u, lds);
         case kBatchFwdCanon:
-          return wide ? pick_onchip<true, kOutCanon, true>(logN, tasks, bk, ctr, claimed, u, lds)
-                      : pick_onchip<true, kOutCanon, false>(logN, tasks, bk, ctr, claimed, u, lds);
+          return wide ? pick_onchip<true, kOutCanon, true>(logN, shape, tasks, bk, ctr, claimed, u, lds)
+                      : pick_onchip<true, kOutCanon, false>(logN, shape, tasks, bk, ctr, claimed, u, lds);
         case kBatchInvLazy:
-          return wide ? pick_onchip<false, kOutLazy, true>(logN, tasks, bk, ctr, claimed, u, lds)
-                      : pick_onchip<false, kOutLazy, false>(logN, tasks, bk, ctr, claimed, u, lds);
+          return wide ? pick_onchip<false, kOutLazy, true>(logN, shape, tasks, bk, ctr, claimed, u, lds)
+                      : pick_onchip<false, kOutLazy, false>(logN, shape, tasks, bk, ctr, claimed, u, lds);
         case kBatchInvCanon:
-          return wide ? pick_onchip<false, kOutCanon, true>(logN, tasks, bk, ctr, claimed, u, lds)
-                      : pick_onchip<false, kOutCanon, false>(logN, tasks, bk, ctr, claimed, u, lds);
+          return wide ? pick_onchip<false, kOutCanon, true>(logN, shape, tasks, bk, ctr, claimed, u, lds)
+                      : pick_onchip<false, kOutCanon, false>(logN, shape, tasks, bk, ctr, claimed, u, lds);
         default: return class_skip(bk, ctr, claimed, u);
       }
     case kClassProduct:
@@ -391,8 +414,8 @@ __device__ __forceinline__ u32 run_class(const BatchTask* tasks, const BatchBloc
         case 17: return class_product_twopass<17>(tasks, bk, ctr, claimed, u, lds);
         default: return class_skip(bk, ctr, claimed, u);
       }
-    case kClassTile0: return pick_tile_op<0>(op, logN, tasks, bk, ctr, claimed, u, lds);
-    case kClassTile1: return pick_tile_op<1>(op, logN, tasks, bk, ctr, claimed, u, lds);
+    case kClassTile0: return pick_tile_op<0>(op, logN, shape, tasks, bk, ctr, claimed, u, lds);
+    case kClassTile1: return pick_tile_op<1>(op, logN, shape, tasks, bk, ctr, claimed, u, lds);
     default: return class_skip(bk, ctr, claimed, u);
   }
 }
@@ -478,19 +501,21 @@ struct TaskClass {
   uint32_t cls, tshift, g;
   uint64_t cost;            // time of one unit, in coefficient-stages per thread (orders the blocks)
 };
-static TaskClass classify(const BatchTask& t) {
+static TaskClass classify(const BatchTask& t, int shape) {
   const uint32_t op = t.op & kBatchOpMask;
   const uint32_t wide = (t.op & kBatchWide) ? 1u : 0u;
   const uint32_t logN = t.logN;
   TaskClass c{};
   if (logN <= (uint32_t)kMaxOnchipLog) {
-    const uint64_t per_thread = (uint64_t)1 << onchip_logr((int)logN);
-    c.g = (uint32_t)onchip_groups((int)logN);
+    // shape 1 for transforms whose limb fits one workgroup at twice the threads (N <= 2^13)
+    const uint32_t sh = (shape == 1 && op != kBatchProduct && logN < (uint32_t)kMaxOnchipLog) ? 1u : 0u;
+    const uint64_t per_thread = (uint64_t)1 << batch_logr((int)logN, (int)sh);
+    c.g = (uint32_t)onchip_groups((int)logN, (int)sh);
     if (op == kBatchProduct) {
       c.cls = kClassProduct | logN << 3 | op << 8 | wide << 11;
       c.cost = 3 * per_thread * logN;
     } else {
-      c.cls = kClassOnchip | logN << 3 | op << 8 | wide << 11;
+      c.cls = kClassOnchip | logN << 3 | op << 8 | wide << 11 | sh << 12;
       c.cost = per_thread * logN;
     }
   } else if (op == kBatchProduct) {
@@ -498,20 +523,15 @@ static TaskClass classify(const BatchTask& t) {
     c.g = 1;
     c.cost = 3 * 8 * (uint64_t)logN << (logN - 12);   // three two-pass transforms of N / 4096 tiles each
   } else {
-    c.cls = kClassTile0 | logN << 3 | op << 8;
+    const uint32_t sh = shape == 1 ? 1u : 0u;
+    c.cls = kClassTile0 | logN << 3 | op << 8 | sh << 12;
     c.tshift = logN - 12;
-    c.g = 2;
-    c.cost = 16 * (uint64_t)(logN + 1) / 2;
+    c.g = sh ? 1 : 2;
+    c.cost = (sh ? 8 : 16) * (uint64_t)(logN + 1) / 2;
   }
   return c;
 }
 
-// Writes a task list into the current staging set as the two phases of one
-// batch: one descriptor per task, ordered by class (longest units first) and,
-// within a class, by (N, q), so that the workgroups running at one time share
-// twiddle tables in L2.  Two-pass transforms (N >= 2^15, not products) run as
-// tiles: the first pass in phase 0, the last pass in phase 1 (same
-// descriptors).  *staged = the number of descriptors.
 // Groups of tasks of one (class, plan): found through a small open-addressing
 // table, so that ordering a batch costs O(tasks) plus a sort of the groups.
 struct TaskGroup {
@@ -571,7 +591,7 @@ static ntt_status stage_units(ntt_batch* b, const std::vector<BatchTask>& list, 
   std::vector<TaskGroup> groups;
   GroupTable table(64);
   for (size_t k = 0; k < n; ++k) {
-    cl[k] = classify(list[k]);
+    cl[k] = classify(list[k], b->shape);
     gid[k] = table.find(groups, cl[k], list[k].plan);
     ++groups[gid[k]].count;
   }
@@ -906,6 +926,20 @@ ntt_status ntt_batch_set_grid(ntt_batch* b, int workgroups) {
   return NTT_OK;
 }
 
+ntt_status ntt_batch_get_config(const ntt_batch* b, int* workgroups, int* shape) {
+  if (!b) return NTT_EINVAL_POINTER;
+  if (workgroups) *workgroups = b->grid;
+  if (shape) *shape = b->shape;
+  return NTT_OK;
+}
+
+ntt_status ntt_batch_set_shape(ntt_batch* b, int shape) {
+  if (!b) return NTT_EINVAL_POINTER;
+  if (shape != 0 && shape != 1) return NTT_EINVAL_COUNT;
+  b->shape = shape;                             // read when a batch is staged; graphs do not depend on it
+  return NTT_OK;
+}
+
 // Validation mode: each task's inputs against its range (forward and product
 // inputs below q, inverse inputs below 2q).
 static ntt_status check_items(const ntt_batch_item* items, size_t count, hipStream_t stream) {
@@ -957,12 +991,13 @@ ntt_status ntt_batch_autotune(ntt_batch* b, const ntt_batch_item* items, size_t 
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return NTT_EDEVICE;
   if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return NTT_EDEVICE; }
-  const int saved = b->grid;
-  int best = saved;
+  const int saved = b->grid, saved_shape = b->shape;
+  int best = saved, best_shape = saved_shape;
   float best_ms = 1e30f;
   ntt_status st = NTT_OK;
-  for (int c = 0; c < 3 && st == NTT_OK; ++c) {
-    b->grid = cand[c];
+  for (int c = 0; c < 6 && st == NTT_OK; ++c) {
+    b->grid = cand[c % 3];
+    b->shape = c / 3;
     st = ntt_batch_run(b, items, count, stream);                 // warm-up
     if (st) break;
     if (hipEventRecord(e0, s) != hipSuccess) { st = NTT_EDEVICE; break; }
@@ -971,13 +1006,15 @@ ntt_status ntt_batch_autotune(ntt_batch* b, const ntt_batch_item* items, size_t 
     if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { st = NTT_EDEVICE; break; }
     float ms = 0;
     (void)hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best_ms) { best_ms = ms; best = cand[c]; }
+    if (ms < best_ms) { best_ms = ms; best = cand[c % 3]; best_shape = c / 3; }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   b->grid = saved;
+  b->shape = saved_shape;
   if (st) return st;
   st = ntt_batch_set_grid(b, best);
+  if (!st) st = ntt_batch_set_shape(b, best_shape);
   if (chosen) *chosen = best;
   return st;
 }

@@ -773,6 +773,35 @@ def test_batch_partial_units_in_place(nt):
     batch.close()
 
 
+def test_batch_shape_one(nt):
+    """Unit shape 1 (twice the threads per limb for N <= 2^13 and per tile of the two-pass sizes;
+    2^14 transforms and products keep shape 0) gives the oracle's results for every op and size,
+    with partial units and transforms in place, plain and graph-replayed."""
+    serving = PRIMES["serving"]["moduli"]
+    specs = []
+    for logN in range(10, 18):
+        for j, op in enumerate((nt.BATCH_FWD_LAZY, nt.BATCH_FWD, nt.BATCH_INV_LAZY, nt.BATCH_INV,
+                                nt.BATCH_PRODUCT)):
+            specs += [(op, logN, serving[(logN + j + r) % len(serving)]) for r in range(3 if logN <= 13 else 1)]
+    tasks, host = _batch_case(nt, 160, specs)
+    for k, t in enumerate(tasks):
+        if t[0] != nt.BATCH_PRODUCT and k % 3 == 1:
+            tasks[k] = (t[0], t[2], t[2], t[3], t[4], t[5], t[6])
+    batch = nt.Batch(len(tasks))
+    assert batch.config() == (0, 0)
+    batch.set_shape(1)
+    with pytest.raises(nt.NttError):
+        batch.set_shape(2)
+    assert batch.config() == (0, 1)
+    batch.run(tasks)
+    _check_batch_outputs(nt, tasks, host)
+    # graph replay on fresh inputs (the in-place tasks consumed theirs)
+    tasks, host = _batch_case(nt, 161, specs)
+    batch.run(tasks, graph=True)
+    _check_batch_outputs(nt, tasks, host)
+    batch.close()
+
+
 def test_batch_item_factors(nt):
     """Per-item input and output factors (the NTT class's input_mod_factor and
     output_mod_factor, Section 4): a batched forward of lazy inputs in [0, 4q) with crafted
