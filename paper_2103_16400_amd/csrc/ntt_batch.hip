@@ -747,10 +747,9 @@ static ntt_status batch_copy(ntt_batch* b, size_t staged, hipStream_t stream) {
              : NTT_EDEVICE;
 }
 
-// Enqueues [phase 0, phase 1] on `stream`; `phase1` false leaves out the second
-// launch (nothing was split).
-ntt_status batch_enqueue(ntt_batch* b, int grid, hipStream_t stream, bool phase1) {
-  ntt_batch_stage& g = cur_stage(b);
+// Enqueues [phase 0, phase 1] of staging set g on `stream`; `phase1` false
+// leaves out the second launch (nothing was split).
+static ntt_status batch_enqueue(ntt_batch_stage& g, int grid, hipStream_t stream, bool phase1) {
   u32* counter = reinterpret_cast<u32*>(g.dev);
   const BatchHead* head = reinterpret_cast<const BatchHead*>(g.dev + kDevHead);
   const BatchTask* tasks = reinterpret_cast<const BatchTask*>(g.dev + kDevHead + kStageHead);
@@ -759,38 +758,48 @@ ntt_status batch_enqueue(ntt_batch* b, int grid, hipStream_t stream, bool phase1
   return hipGetLastError() == hipSuccess ? NTT_OK : NTT_EDEVICE;
 }
 
+// Captures staging set sg's [phase 0, phase 1] with the full grid: the kernels
+// read the blocks and counts from device memory.
+static ntt_status batch_capture(ntt_batch* b, ntt_batch_stage& sg) {
+  const int grid = batch_grid(b, (size_t)1 << 30);
+  hipStream_t cap = nullptr;
+  if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return NTT_EDEVICE;
+  if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipStreamDestroy(cap);
+    return NTT_EDEVICE;
+  }
+  const ntt_status st = batch_enqueue(sg, grid, cap, true);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(cap, &g);
+  (void)hipStreamDestroy(cap);
+  if (st) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess || !g) return NTT_EDEVICE;
+  if (hipGraphInstantiate(&sg.graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    sg.graph_exec = nullptr;
+    (void)hipGraphDestroy(g);
+    return NTT_EDEVICE;
+  }
+  sg.graph = g;
+  return NTT_OK;
+}
+
 static ntt_status batch_launch_staged(ntt_batch* b, size_t n, hipStream_t s, bool graph) {
   ntt_batch_stage& sg = cur_stage(b);
   ntt_status st = batch_copy(b, n, s);
   if (st) return st;
   if (!graph) {
     const BatchHead* head = reinterpret_cast<const BatchHead*>(sg.host);
-    st = batch_enqueue(b, batch_grid(b, std::max(head->units[0], head->units[1])), s, head->units[1] != 0);
+    st = batch_enqueue(sg, batch_grid(b, std::max(head->units[0], head->units[1])), s, head->units[1] != 0);
     if (st) return st;
   } else {
-    if (!sg.graph_exec) {
-      // captured once per staging set with the full grid; the kernels read the blocks and counts from device memory
-      const int grid = batch_grid(b, (size_t)1 << 30);
-      hipStream_t cap = nullptr;
-      if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return NTT_EDEVICE;
-      if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-        (void)hipStreamDestroy(cap);
-        return NTT_EDEVICE;
-      }
-      st = batch_enqueue(b, grid, cap, true);
-      hipGraph_t g = nullptr;
-      const hipError_t e = hipStreamEndCapture(cap, &g);
-      (void)hipStreamDestroy(cap);
-      if (st) {
-        if (g) (void)hipGraphDestroy(g);
-        return st;
-      }
-      if (e != hipSuccess || !g) return NTT_EDEVICE;
-      if (hipGraphInstantiate(&sg.graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
-        (void)hipGraphDestroy(g);
-        return NTT_EDEVICE;
-      }
-      sg.graph = g;
+    // both staging sets are captured at once, so that no later run pays for an instantiation
+    for (ntt_batch_stage& h : b->stage) {
+      if (h.graph_exec) continue;
+      st = batch_capture(b, h);
+      if (st) return st;
     }
     if (hipGraphLaunch(sg.graph_exec, s) != hipSuccess) return NTT_EDEVICE;
   }
