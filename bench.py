@@ -239,7 +239,8 @@ def time_uneven_batch(nt, torch, primes, reps=10):
 
 def time_batch_one_size(nt, torch, primes, logN, polys=320, reps=10):
     """5120 limbs of one ring degree (320 polynomials x the 16 primes of the uneven pool), forward
-    1 -> 4: the persistent batch (plain launches, grid of two workgroups per CU) against one
+    1 -> 4: the persistent batch (plain launches, grid of two workgroups per CU; unit shape 0,
+    then 1) against one
     `ntt_forward_rns` launch over the same limbs.  Event-timed calls include the host's
     preparation of each batch; a kernel trace of this mode gives the kernels' own durations."""
     from synthetic import uniform_mod, unit_seed
@@ -265,8 +266,10 @@ def time_batch_one_size(nt, torch, primes, logN, polys=320, reps=10):
         torch.cuda.synchronize()
         return round(e0.elapsed_time(e1) * 1e3 / reps, 1)
     res = {"logN": logN, "limbs": polys * L,
-           "batch_us": timed(lambda: batch.run(items, cnt, stream=stream)),
-           "rns_us": timed(lambda: nt.ntt_forward_rns(dst, src, N, pool, polys, 1, 4, stream=stream))}
+           "batch_us": timed(lambda: batch.run(items, cnt, stream=stream))}
+    batch.set_shape(1)
+    res["batch_shape1_us"] = timed(lambda: batch.run(items, cnt, stream=stream))
+    res["rns_us"] = timed(lambda: nt.ntt_forward_rns(dst, src, N, pool, polys, 1, 4, stream=stream))
     batch.close()
     return res
 
