@@ -393,8 +393,9 @@ ntt_status poly_mul_acc_ntt_rns32(uint32_t* acc, const uint32_t* a_ntt, const ui
  *   on: 0 (default) the per-call kernels' own (16 or 32 coefficients per
  *   thread, several limbs per workgroup below 2^14, tiles of 16 per thread);
  *   1 twice the threads per limb or tile (for N <= 2^13 and for the tiles of
- *   N >= 2^15; N = 2^14 transforms and products keep shape 0).  Results are
- *   the same words either way.  NTT_EINVAL_COUNT for another value.
+ *   N >= 2^15; N = 2^14 transforms and products keep shape 0); 2 twice the
+ *   threads per tile only (limbs as in shape 0).  Results are the same words
+ *   whichever the shape.  NTT_EINVAL_COUNT for another value.
  * ntt_batch_get_config: the context's workgroup count (0 = automatic) and
  *   unit shape, as set or chosen by ntt_batch_autotune (either pointer may be
  *   NULL).
@@ -424,7 +425,7 @@ ntt_status ntt_batch_get_config(const ntt_batch* batch, int* workgroups, int* sh
 ntt_status ntt_batch_run(ntt_batch* batch, const ntt_batch_item* items, size_t count, ntt_stream_t stream);
 ntt_status ntt_batch_run_graph(ntt_batch* batch, const ntt_batch_item* items, size_t count, ntt_stream_t stream);
 /* Times the persistent launch of this batch with one, one and a half and two
- * workgroups per CU, each with both unit shapes (ntt_batch_set_shape), and
+ * workgroups per CU, each with the three unit shapes (ntt_batch_set_shape), and
  * keeps the fastest grid and shape for the context (the chosen workgroup
  * count in *chosen, may be NULL).  Runs the batch several times, so every
  * task must have out != in (NTT_EALIAS otherwise); outputs end up holding the

@@ -334,7 +334,7 @@ class Batch:
         _check(_lib.ntt_batch_set_grid(self._h, workgroups), "ntt_batch_set_grid")
 
     def set_shape(self, shape: int):
-        """0: the per-call kernels' shapes; 1: twice the threads per limb or tile."""
+        """0: the per-call kernels' shapes; 1: twice the threads per limb or tile; 2: per tile only."""
         _check(_lib.ntt_batch_set_shape(self._h, shape), "ntt_batch_set_shape")
 
     def config(self):

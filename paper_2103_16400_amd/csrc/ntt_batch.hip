@@ -51,7 +51,7 @@ struct ntt_batch {
   int device;
   size_t capacity;                 // tasks
   int grid;                        // persistent workgroups (0: automatic)
-  int shape;                       // per-limb shape of transform units: 0 the single-pass kernel's, 1 twice the threads
+  int shape;                       // unit shapes: 0 the per-call kernels', 1 twice the threads per limb and tile, 2 per tile only
   int cur;                         // staging set of the next run
   hipStream_t copy_stream;         // runs copy their descriptors here, overlapping the previous run
   bool use_copy_stream;            // off: copies go on the launch stream (callers that own several streams)
@@ -523,7 +523,7 @@ static TaskClass classify(const BatchTask& t, int shape) {
     c.g = 1;
     c.cost = 3 * 8 * (uint64_t)logN << (logN - 12);   // three two-pass transforms of N / 4096 tiles each
   } else {
-    const uint32_t sh = shape == 1 ? 1u : 0u;
+    const uint32_t sh = shape >= 1 ? 1u : 0u;       // shapes 1 and 2
     c.cls = kClassTile0 | logN << 3 | op << 8 | sh << 12;
     c.tshift = logN - 12;
     c.g = sh ? 1 : 2;
@@ -944,7 +944,7 @@ ntt_status ntt_batch_get_config(const ntt_batch* b, int* workgroups, int* shape)
 
 ntt_status ntt_batch_set_shape(ntt_batch* b, int shape) {
   if (!b) return NTT_EINVAL_POINTER;
-  if (shape != 0 && shape != 1) return NTT_EINVAL_COUNT;
+  if (shape < 0 || shape > 2) return NTT_EINVAL_COUNT;
   b->shape = shape;                             // read when a batch is staged; graphs do not depend on it
   return NTT_OK;
 }
@@ -1004,7 +1004,7 @@ ntt_status ntt_batch_autotune(ntt_batch* b, const ntt_batch_item* items, size_t 
   int best = saved, best_shape = saved_shape;
   float best_ms = 1e30f;
   ntt_status st = NTT_OK;
-  for (int c = 0; c < 6 && st == NTT_OK; ++c) {
+  for (int c = 0; c < 9 && st == NTT_OK; ++c) {
     b->grid = cand[c % 3];
     b->shape = c / 3;
     st = ntt_batch_run(b, items, count, stream);                 // warm-up

@@ -773,10 +773,12 @@ def test_batch_partial_units_in_place(nt):
     batch.close()
 
 
-def test_batch_shape_one(nt):
+@pytest.mark.parametrize("shape", [1, 2])
+def test_batch_shape_one(nt, shape):
     """Unit shape 1 (twice the threads per limb for N <= 2^13 and per tile of the two-pass sizes;
-    2^14 transforms and products keep shape 0) gives the oracle's results for every op and size,
-    with partial units and transforms in place, plain and graph-replayed."""
+    2^14 transforms and products keep shape 0) and shape 2 (twice the threads per tile only) give
+    the oracle's results for every op and size, with partial units and transforms in place, plain
+    and graph-replayed."""
     serving = PRIMES["serving"]["moduli"]
     specs = []
     for logN in range(10, 18):
@@ -789,10 +791,11 @@ def test_batch_shape_one(nt):
             tasks[k] = (t[0], t[2], t[2], t[3], t[4], t[5], t[6])
     batch = nt.Batch(len(tasks))
     assert batch.config() == (0, 0)
-    batch.set_shape(1)
-    with pytest.raises(nt.NttError):
-        batch.set_shape(2)
-    assert batch.config() == (0, 1)
+    batch.set_shape(shape)
+    for bad in (-1, 3):
+        with pytest.raises(nt.NttError):
+            batch.set_shape(bad)
+    assert batch.config() == (0, shape)
     batch.run(tasks)
     _check_batch_outputs(nt, tasks, host)
     # graph replay on fresh inputs (the in-place tasks consumed theirs)
