@@ -445,8 +445,8 @@ ntt_status ntt_batch_autotune(ntt_batch* batch, const ntt_batch_item* items, siz
 /* ---------------------------------------------------------------------------
  * Autotuning (Section 4 notes that the best implementation can be picked by
  * trying the candidates at initialisation).  For two-pass sizes (N > 2^14) the
- * library has several kernel variants per pass (thread shapes and N1 x N2
- * splits), for N = 2^10 .. 2^14 two thread shapes of the single-pass kernel
+ * library has several kernel variants per pass (thread shapes, N1 x N2 splits
+ * and a three-pass split), for N = 2^10 .. 2^14 two thread shapes of the single-pass kernel
  * (variant 1 gives each limb twice the threads); this call times each, 20
  * launches per variant, on scratch operand sets of num_limbs * num_polys * N
  * words used in turn (enough sets, up to 32, that they exceed the 256 MB MALL,

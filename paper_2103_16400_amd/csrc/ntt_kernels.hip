@@ -17,7 +17,9 @@
 // C = 2^LOGC adjacent columns, lanes running along the columns so every HBM
 // access covers C contiguous words; the "low" pass (b0 = 0) gives it H = 2^LOGH
 // adjacent contiguous blocks.  Forward passes run high then low, inverse
-// passes low then high.
+// passes low then high.  A three-pass schedule (N = N1 N2 N3) adds a middle
+// pass: strided like the high pass, with the bits above its range selecting
+// independent blocks of sub-transforms.
 //
 // Inside a tile each thread holds R = 2^LOGR coefficients and runs up to
 // LOGR stages per round in registers; rounds exchange through LDS (rows
@@ -83,12 +85,14 @@ typedef void (*PassKernel)(const PassArgs);
 // exceed 1024 threads of 8 coefficients.  Variants 8 and 9 halve both passes'
 // tiles (half the columns per high-pass tile, half the blocks per low-pass
 // tile): twice the workgroups, for batches too small to fill the chip.
-constexpr int kVariants = 10;
-struct VariantShape { int hi, lo; bool hand; int dlo; int half; };
+// Variant 10 splits N three ways (see three_pass_split) at 8 coefficients per
+// thread: one more pass over HBM, fewer stages per pass.
+constexpr int kVariants = 11;
+struct VariantShape { int hi, lo; bool hand; int dlo; int half; int passes = 2; };
 static constexpr VariantShape kVariantShape[kVariants] = {
     {4, 4, true, 0, 0}, {3, 4, true, 0, 0}, {2, 4, true, 0, 0}, {3, 3, true, 0, 0},
     {2, 3, true, 0, 0}, {2, 2, false, 0, 0}, {3, 4, true, -1, 0}, {3, 4, true, 1, 0},
-    {3, 4, true, 0, 1}, {2, 4, true, 0, 1}};
+    {3, 4, true, 0, 1}, {2, 4, true, 0, 1}, {3, 3, true, 0, 0, 3}};
 // Index bits of the low pass for a variant, and columns per high-pass tile.
 static int variant_lt_lo(int logN, int variant) { return mp_logt_lo(logN) + kVariantShape[variant].dlo; }
 __host__ __device__ constexpr int hi_logc(int lt_hi) { return lt_hi >= 10 ? 3 : 4; }
@@ -163,6 +167,54 @@ static PassKernel pick_pass_n(int logN, bool fwd, bool hi, u32 flags, int varian
   }
 }
 
+// Three-pass split N = 2^LT_HIGH * 2^lt_mid * 2^lt_low: index bits [0, low) in
+// the low pass, [low, low + mid) in the middle pass, the top LT_HIGH bits in
+// the high pass (2^15: 5 + 5 + 5, 2^16: 6 + 5 + 5, 2^17: 6 + 6 + 5).  Tiles hold
+// 4096 coefficients, except the middle pass's columns, which stay inside the
+// low pass's bits (2048 coefficients at 2^16, 1024 at 2^15).
+constexpr int kThreeHigh = 5;
+__host__ __device__ constexpr int three_low(int logN) { return logN == 15 ? 5 : 6; }
+__host__ __device__ constexpr int three_mid(int logN) { return logN - kThreeHigh - three_low(logN); }
+__host__ __device__ constexpr int three_mid_logc(int logN) {
+  return 12 - three_mid(logN) < three_low(logN) ? 12 - three_mid(logN) : three_low(logN);
+}
+constexpr int kThreeLogr = 3;
+
+// Kernel of pass `which` (0 high, 1 middle, 2 low) of the three-pass schedule.
+template <bool FWD, int LOGN, int WHICH, int MODE, bool LAST>
+static PassKernel pick_three_r() {
+  if constexpr (WHICH == 0)
+    return ntt_tile_kernel<FWD, kThreeHigh, kThreeLogr, 12 - kThreeHigh, 0, 4, MODE, LAST, -1>;
+  else if constexpr (WHICH == 1)
+    return ntt_tile_kernel<FWD, three_mid(LOGN), kThreeLogr, three_mid_logc(LOGN), 0, 4, MODE, LAST, -1>;
+  else
+    return ntt_tile_kernel<FWD, three_low(LOGN), kThreeLogr, 0, 12 - three_low(LOGN), 4, MODE, LAST, -1>;
+}
+// Forward: high, middle, low (the low pass last); inverse: low, middle, high.
+template <int LOGN>
+static PassKernel pick_three(bool fwd, int which, u32 flags) {
+  if (fwd) {
+    if (which == 0) return pick_three_r<true, LOGN, 0, kOutLazy, false>();
+    if (which == 1) return pick_three_r<true, LOGN, 1, kOutLazy, false>();
+    if (flags & kFlagMul) return pick_three_r<true, LOGN, 2, kOutMul, true>();
+    if (flags & kFlagCanon) return pick_three_r<true, LOGN, 2, kOutCanon, true>();
+    return pick_three_r<true, LOGN, 2, kOutLazy, true>();
+  }
+  if (which == 2) return pick_three_r<false, LOGN, 2, kOutLazy, false>();
+  if (which == 1) return pick_three_r<false, LOGN, 1, kOutLazy, false>();
+  if (flags & kFlagAcc) return pick_three_r<false, LOGN, 0, kOutAcc, true>();
+  if (flags & kFlagCanon) return pick_three_r<false, LOGN, 0, kOutCanon, true>();
+  return pick_three_r<false, LOGN, 0, kOutLazy, true>();
+}
+static PassKernel pick_three_n(int logN, bool fwd, int which, u32 flags) {
+  switch (logN) {
+    case 15: return pick_three<15>(fwd, which, flags);
+    case 16: return pick_three<16>(fwd, which, flags);
+    case 17: return pick_three<17>(fwd, which, flags);
+    default: return nullptr;
+  }
+}
+
 // Number of passes the schedule for 2^logN uses (1 = the whole transform on chip).
 int pass_count(int logN) { return logN <= kMaxOnchipLog ? 1 : 2; }
 
@@ -228,9 +280,34 @@ static ntt_status launch_passes(const NttLaunch& l, bool fwd, int force_variant)
   if (logN > NTT_MAX_LOG_DEGREE) return NTT_EINVAL_DEGREE;
   const int variant = force_variant >= 0 ? force_variant : get_hi_variant(fwd, logN, items);
   if (variant < 0 || variant >= kVariants) return NTT_EINVAL_COUNT;
-  const int lt_lo = variant_lt_lo(logN, variant), lt_hi = logN - lt_lo;
   uint64_t* mid = l.tmp ? l.tmp : l.out;
   const uint64_t kMaxY = 65535;
+  if (kVariantShape[variant].passes == 3) {
+    // bit ranges (b0, bits, columns or blocks) of the high, middle and low passes
+    const int low = three_low(logN), midb = three_mid(logN);
+    for (int step = 0; step < 3; ++step) {
+      const int which = fwd ? step : 2 - step;
+      const bool last = step == 2;
+      a.in = step == 0 ? l.in : mid;
+      a.out = last ? l.out : mid;
+      a.flags = last ? last_flags : 0u;
+      PassKernel k = pick_three_n(logN, fwd, which, a.flags);
+      if (!k) return NTT_EINVAL_DEGREE;
+      int bits, logc, logh;
+      if (which == 0) { a.b0 = (u32)(low + midb); bits = kThreeHigh; logc = 12 - kThreeHigh; logh = 0; }
+      else if (which == 1) { a.b0 = (u32)low; bits = midb; logc = three_mid_logc(logN); logh = 0; }
+      else { a.b0 = 0; bits = low; logc = 0; logh = 12 - low; }
+      const int nt = 1 << (bits + logc + logh - kThreeLogr);
+      const uint64_t tiles = 1ull << (logN - bits - logc - logh);
+      for (uint64_t it0 = 0; it0 < items; it0 += kMaxY) {
+        const uint64_t ny = (items - it0) < kMaxY ? (items - it0) : kMaxY;
+        a.item0 = (u32)it0;
+        hipLaunchKernelGGL(k, dim3((unsigned)tiles, (unsigned)ny), dim3(nt), 0, l.stream, a);
+      }
+    }
+    return hipGetLastError() == hipSuccess ? NTT_OK : NTT_EDEVICE;
+  }
+  const int lt_lo = variant_lt_lo(logN, variant), lt_hi = logN - lt_lo;
   for (int step = 0; step < 2; ++step) {
     const bool hi = fwd ? (step == 0) : (step == 1);
     const bool last = step == 1;

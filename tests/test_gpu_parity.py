@@ -361,7 +361,7 @@ def test_two_pass_schedule_variants(nt, logN):
     full_fwd = [oracle.harvey_forward(a[l * N:(l + 1) * N], q, psis[l], 1) for l, q in enumerate(moduli)]
     full_inv = [oracle.harvey_inverse(A[l * N:(l + 1) * N], q, psis[l], 1) for l, q in enumerate(moduli)]
     nv = _variant_count(nt, N)
-    assert nv >= 10                     # thread shapes, half-size tiles and the two alternative splits
+    assert nv >= 11                     # thread shapes, half-size tiles, two other splits, three passes
     ws = empty_dev(L * N)
     try:
         for v in range(nv):
