@@ -46,7 +46,7 @@ HBM_PEAK_GBS = 8000.0
 # Valid only for the kernel sources they were taken with, identified by the SHA-256 of these files.
 COUNTERS_N16384 = {
     "sources": ["ntt_onchip.hip", "ntt_onchip.h", "ntt_common.h", "modarith.h", "internal.h", "ntt_kernels.hip"],
-    "sha256": "572777454cf7cc023cf82a44b846408e1c281ed910f25c3bb113182690c1be72",
+    "sha256": "081aafeb2850f1786c03544fc47790fbf1888847fb7cf0b76e47424e4560a928",
     "fetch_scale": 2.0, "write_scale": 1.0,
     "product": {"fetch_kib": 886963.8, "write_kib": 540672.0, "valu_insts": 394428416},
     "forward": {"fetch_kib": 294642.5, "write_kib": 581632.0, "valu_insts": 145195008},
