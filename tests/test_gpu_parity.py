@@ -879,16 +879,18 @@ def test_batch_counters_across_grids_and_modes(nt):
     """Each phase's claim counter is cleared by the workgroup that draws the phase's last claim
     (units + grid - 1), so it must hold whatever the grid and however plain and graph-replayed
     runs alternate: a grid smaller than the units, one larger than them, a change of grid between
-    runs, batches with and without a second phase, all against the oracle."""
+    runs, a change of unit shape (other block layouts on the same counters), batches with and
+    without a second phase, all against the oracle."""
     moduli = PRIMES["uneven"]["moduli"]
     with_split = [(nt.BATCH_FWD_LAZY, 12 + (k % 4), moduli[k % 16]) for k in range(9)]   # 2^15 limbs too
     no_split = [(nt.BATCH_INV, 10 + (k % 3), moduli[(5 * k) % 16]) for k in range(7)]
     cases = [_batch_case(nt, 150, with_split), _batch_case(nt, 151, no_split)]
     batch = nt.Batch(16)
     import torch
-    for rnd, (grid, graph) in enumerate([(0, False), (3, False), (3, True), (1000, False), (1000, True),
-                                         (0, True), (5, False)]):
+    for rnd, (grid, graph, shape) in enumerate([(0, False, 0), (3, False, 1), (3, True, 2), (1000, False, 2),
+                                                (1000, True, 0), (0, True, 1), (5, False, 0)]):
         batch.set_grid(grid)
+        batch.set_shape(shape)
         for tasks, host in cases:
             for t in tasks:
                 t[1].zero_()
