@@ -201,9 +201,16 @@ __device__ __forceinline__ u32 run_block(const BatchBlock& bk_in, u32* ctr_in, u
   }
 }
 
+// Class bodies are inlined into the kernel for the classes a batch holds most
+// often (the wide-range single-pass transforms, the tiles at twice the threads:
+// see pick_onchip and pick_tile); the other classes run as separate functions,
+// which bounds the build's size and time but costs a call: the callee saves and
+// restores 48 VGPRs per lane (192 KiB per workgroup) each time a workgroup
+// enters such a block.
+
 // Whole single-pass transforms (N <= 2^14).
 template <bool FWD, int LOGN, int MODE, bool WIDE, int SHAPE = 0>
-__device__ __attribute__((noinline)) u32 class_onchip(const BatchTask* tasks, const BatchBlock bk, u32* ctr,
+__device__ __forceinline__ u32 class_onchip_in(const BatchTask* tasks, const BatchBlock& bk, u32* ctr,
                                                       u32* claimed, u32 u, u32* lds) {
   constexpr int LOGR = batch_logr(LOGN, SHAPE);
   constexpr bool SPLIT = LOGN >= 13;
@@ -217,6 +224,12 @@ __device__ __attribute__((noinline)) u32 class_onchip(const BatchTask* tasks, co
     typename K::W* l = reinterpret_cast<typename K::W*>(lds) + h * K::LDSW;
     onchip_body<FWD, LOGN, LOGR, SPLIT, MODE, true, WIDE, true>(pv, tk.in, tk.out, nullptr, l, true, t, active);
   });
+}
+
+template <bool FWD, int LOGN, int MODE, bool WIDE, int SHAPE = 0>
+__device__ __attribute__((noinline)) u32 class_onchip(const BatchTask* tasks, const BatchBlock bk, u32* ctr,
+                                                      u32* claimed, u32 u, u32* lds) {
+  return class_onchip_in<FWD, LOGN, MODE, WIDE, SHAPE>(tasks, bk, ctr, claimed, u, lds);
 }
 
 // Whole products on chip: out <- NTT(a) lazy, then out <- InvNTT(NTT(b) (.) out)
@@ -293,7 +306,7 @@ __device__ __attribute__((noinline)) u32 class_product_twopass(const BatchTask* 
 // low pass reads the transposed sub-tables).  Sub-task k is tile k mod T of the
 // block's task k / T, T = N / 4096.
 template <bool FWD, int LOGN, int MODE, int PASS, int SHAPE = 0>
-__device__ __attribute__((noinline)) u32 class_tile(const BatchTask* tasks, const BatchBlock bk, u32* ctr,
+__device__ __forceinline__ u32 class_tile_in(const BatchTask* tasks, const BatchBlock& bk, u32* ctr,
                                                     u32* claimed, u32 u, u32* lds) {
   constexpr int LT_LO = mp_logt_lo(LOGN);
   constexpr int LT_HI = LOGN - LT_LO;
@@ -327,6 +340,12 @@ __device__ __attribute__((noinline)) u32 class_tile(const BatchTask* tasks, cons
   });
 }
 
+template <bool FWD, int LOGN, int MODE, int PASS, int SHAPE = 0>
+__device__ __attribute__((noinline)) u32 class_tile(const BatchTask* tasks, const BatchBlock bk, u32* ctr,
+                                                    u32* claimed, u32 u, u32* lds) {
+  return class_tile_in<FWD, LOGN, MODE, PASS, SHAPE>(tasks, bk, ctr, claimed, u, lds);
+}
+
 // A block of a class this kernel does not know: claims past it.
 __device__ __attribute__((noinline)) u32 class_skip(const BatchBlock bk, u32* ctr, u32* claimed, u32 u) {
   return run_block(bk, ctr, claimed, u, 1, [](u32, u32, bool, u32) {});
@@ -344,6 +363,16 @@ __device__ __forceinline__ u32 pick_onchip(u32 logN, u32 shape, const BatchTask*
       default: return class_skip(bk, ctr, claimed, u);
     }
   }
+  if constexpr (WIDE) {                         // inlined: the usual case (moduli below 2^58)
+    switch (logN) {
+      case 10: return class_onchip_in<FWD, 10, MODE, true>(tasks, bk, ctr, claimed, u, lds);
+      case 11: return class_onchip_in<FWD, 11, MODE, true>(tasks, bk, ctr, claimed, u, lds);
+      case 12: return class_onchip_in<FWD, 12, MODE, true>(tasks, bk, ctr, claimed, u, lds);
+      case 13: return class_onchip_in<FWD, 13, MODE, true>(tasks, bk, ctr, claimed, u, lds);
+      case 14: return class_onchip_in<FWD, 14, MODE, true>(tasks, bk, ctr, claimed, u, lds);
+      default: break;
+    }
+  }
   switch (logN) {
     case 10: return class_onchip<FWD, 10, MODE, WIDE>(tasks, bk, ctr, claimed, u, lds);
     case 11: return class_onchip<FWD, 11, MODE, WIDE>(tasks, bk, ctr, claimed, u, lds);
@@ -357,6 +386,14 @@ __device__ __forceinline__ u32 pick_onchip(u32 logN, u32 shape, const BatchTask*
 template <bool FWD, int MODE, int PASS>
 __device__ __forceinline__ u32 pick_tile(u32 logN, u32 shape, const BatchTask* tasks, const BatchBlock& bk, u32* ctr,
                                          u32* claimed, u32 u, u32* lds) {
+  if (shape) {                                  // inlined: the autotuner's usual choice
+    switch (logN) {
+      case 15: return class_tile_in<FWD, 15, MODE, PASS, 1>(tasks, bk, ctr, claimed, u, lds);
+      case 16: return class_tile_in<FWD, 16, MODE, PASS, 1>(tasks, bk, ctr, claimed, u, lds);
+      case 17: return class_tile_in<FWD, 17, MODE, PASS, 1>(tasks, bk, ctr, claimed, u, lds);
+      default: break;
+    }
+  }
   switch (logN * 2 + (shape ? 1 : 0)) {
     case 30: return class_tile<FWD, 15, MODE, PASS>(tasks, bk, ctr, claimed, u, lds);
     case 31: return class_tile<FWD, 15, MODE, PASS, 1>(tasks, bk, ctr, claimed, u, lds);
